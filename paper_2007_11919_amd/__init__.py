@@ -1,0 +1,12 @@
+"""Interpolation MDS (Delicado and Pachon-Garcia, Section 3.1) on one MI355X.
+
+The work runs in libmds.so (HIP for gfx950, C ABI in include/mds.h); this
+package only marshals arguments.  There is no CPU fallback: if the library
+is missing every call raises.
+"""
+
+from .api import (F32, F64, PREC, MDSError, Model, embed, fit_landmarks, free,
+                  sample_landmarks)
+
+__all__ = ["F32", "F64", "PREC", "MDSError", "Model", "embed", "fit_landmarks", "free",
+           "sample_landmarks"]

@@ -1,0 +1,230 @@
+// C ABI entry points of libmds: argument validation, model lifetime, and
+// dispatch to the HIP kernels.  Semantics are documented in include/mds.h.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mds_internal.h"
+
+struct mds_model {
+  mds::Model m;
+};
+
+namespace mds {
+
+namespace {
+thread_local std::string g_err;
+thread_local int32_t g_hip_err = 0;
+}  // namespace
+
+mds_status set_error(mds_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+mds_status hip_fail(hipError_t e, const char* what) {
+  g_hip_err = (int32_t)e;
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? MDS_ERR_OOM : MDS_ERR_HIP;
+}
+
+namespace {
+
+void free_model(Model& m) {
+  void* bufs[] = {m.m64, m.m32, m.mbf, m.mh, m.w32, m.w64, m.c32, m.c64};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete[] m.idx_host;
+  delete[] m.lam_host;
+  delete[] m.x1_host;
+  delete[] m.q_host;
+  m = Model();
+}
+
+}  // namespace
+}  // namespace mds
+
+using namespace mds;
+
+extern "C" {
+
+const char* mds_last_error(void) { return g_err.c_str(); }
+int32_t mds_last_hip_error(void) { return g_hip_err; }
+
+mds_status mds_sample_landmarks(int64_t n, int64_t l, uint64_t seed, int64_t* idx_out) {
+  if (!idx_out) return set_error(MDS_ERR_INVALID_ARG, "idx_out is NULL");
+  if (l < 1 || l > n) return set_error(MDS_ERR_INVALID_ARG, "need 1 <= l <= n");
+  try {
+    sample_landmarks_host(n, l, seed, idx_out);
+  } catch (const std::bad_alloc&) {
+    return set_error(MDS_ERR_OOM, "host allocation failed in sampler");
+  }
+  return MDS_OK;
+}
+
+mds_status mds_fit_landmarks(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
+                             int32_t r, uint64_t seed, const int64_t* idx_or_null, void* stream,
+                             mds_model** out) {
+  if (!out) return set_error(MDS_ERR_INVALID_ARG, "out is NULL");
+  if (!X) return set_error(MDS_ERR_INVALID_ARG, "X is NULL");
+  if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
+  if (p < 1) return set_error(MDS_ERR_INVALID_ARG, "p must be >= 1");
+  if (ldx < p) return set_error(MDS_ERR_INVALID_ARG, "ldx < p");
+  if (l < 2 || l > n) return set_error(MDS_ERR_INVALID_ARG, "need 2 <= l <= n");
+  if (r < 1 || r > l - 1 || r > MDS_MAX_R)
+    return set_error(MDS_ERR_INVALID_ARG, "need 1 <= r <= min(l - 1, MDS_MAX_R)");
+  if (p > (int64_t)1 << 24) return set_error(MDS_ERR_INVALID_ARG, "p too large");
+  if (l > (int64_t)1 << 16) return set_error(MDS_ERR_INVALID_ARG, "l too large (max 65536)");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+
+  mds_model* h = nullptr;
+  try {
+    h = new mds_model();
+    Model& m = h->m;
+    m.n_fit = n;
+    m.p = p;
+    m.l = l;
+    m.l_pad = round_up(l, BN);
+    m.r = r;
+    m.rb = (int32_t)((r + 15) / 16);
+    if (m.rb == 3) m.rb = 4;
+    (void)hipGetDevice(&m.dev);
+    m.idx_host = new int64_t[(size_t)l];
+    if (idx_or_null) {
+      std::vector<int64_t> v(idx_or_null, idx_or_null + l);
+      std::sort(v.begin(), v.end());
+      for (int64_t i = 0; i < l; ++i) {
+        if (v[i] < 0 || v[i] >= n) {
+          free_model(m);
+          delete h;
+          return set_error(MDS_ERR_INVALID_ARG, "landmark index out of range");
+        }
+        if (i > 0 && v[i] == v[i - 1]) {
+          free_model(m);
+          delete h;
+          return set_error(MDS_ERR_INVALID_ARG, "duplicate landmark index");
+        }
+      }
+      std::memcpy(m.idx_host, v.data(), sizeof(int64_t) * l);
+    } else {
+      sample_landmarks_host(n, l, seed, m.idx_host);
+    }
+  } catch (const std::bad_alloc&) {
+    if (h) {
+      free_model(h->m);
+      delete h;
+    }
+    return set_error(MDS_ERR_OOM, "host allocation failed");
+  }
+  Model& m = h->m;
+  int64_t* idx_dev = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&idx_dev), sizeof(int64_t) * l, st);
+  if (e != hipSuccess) {
+    free_model(m);
+    delete h;
+    return hip_fail(e, "hipMallocAsync(idx)");
+  }
+  e = hipMemcpyAsync(idx_dev, m.idx_host, sizeof(int64_t) * l, hipMemcpyHostToDevice, st);
+  mds_status s = (e == hipSuccess) ? fit_on_device(m, X, dt, ldx, idx_dev, st)
+                                   : hip_fail(e, "hipMemcpyAsync(idx)");
+  (void)hipFreeAsync(idx_dev, st);
+  if (s == MDS_OK) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = hip_fail(e, "fit synchronize");
+  } else {
+    (void)hipStreamSynchronize(st);
+  }
+  if (s != MDS_OK) {
+    free_model(m);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return MDS_OK;
+}
+
+mds_status mds_embed(const mds_model* h, const void* X, int32_t dt, int64_t n_new, int64_t ldx,
+                     int32_t prec, void* Y, int64_t ldy, void* stream) {
+  if (!h) return set_error(MDS_ERR_INVALID_ARG, "model is NULL");
+  const Model& m = h->m;
+  if (n_new < 0) return set_error(MDS_ERR_INVALID_ARG, "n_new < 0");
+  if (prec < MDS_PREC_FP64 || prec > MDS_PREC_SPLIT_FP16)
+    return set_error(MDS_ERR_INVALID_ARG, "unknown precision");
+  if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
+  if (prec != MDS_PREC_FP64 && dt != MDS_F32)
+    return set_error(MDS_ERR_INVALID_ARG, "FP32 and split precisions take MDS_F32 input");
+  if (n_new == 0) return MDS_OK;
+  if (!X || !Y) return set_error(MDS_ERR_INVALID_ARG, "X or Y is NULL");
+  if (ldx < m.p) return set_error(MDS_ERR_INVALID_ARG, "ldx < p");
+  if (ldy < m.r) return set_error(MDS_ERR_INVALID_ARG, "ldy < r");
+  int mode = MODE_F32;
+  switch (prec) {
+    case MDS_PREC_FP64: mode = MODE_F64; break;
+    case MDS_PREC_FP32: mode = MODE_F32; break;
+    case MDS_PREC_SPLIT_BF16: mode = MODE_BF16; break;
+    default: mode = MODE_F16; break;
+  }
+  return launch_embed(m, mode, X, dt, n_new, ldx, Y, ldy, reinterpret_cast<hipStream_t>(stream));
+}
+
+void mds_free(mds_model* h) {
+  if (!h) return;
+  free_model(h->m);
+  delete h;
+}
+
+mds_status mds_model_info(const mds_model* h, int64_t* n_fit, int64_t* p, int64_t* l, int32_t* r,
+                          int32_t* r_eff) {
+  if (!h) return set_error(MDS_ERR_INVALID_ARG, "model is NULL");
+  if (n_fit) *n_fit = h->m.n_fit;
+  if (p) *p = h->m.p;
+  if (l) *l = h->m.l;
+  if (r) *r = h->m.r;
+  if (r_eff) *r_eff = h->m.r_eff;
+  return MDS_OK;
+}
+
+mds_status mds_get_landmarks(const mds_model* h, int64_t* idx) {
+  if (!h || !idx) return set_error(MDS_ERR_INVALID_ARG, "NULL argument");
+  std::memcpy(idx, h->m.idx_host, sizeof(int64_t) * h->m.l);
+  return MDS_OK;
+}
+
+mds_status mds_get_eigenvalues(const mds_model* h, double* lam) {
+  if (!h || !lam) return set_error(MDS_ERR_INVALID_ARG, "NULL argument");
+  std::memcpy(lam, h->m.lam_host, sizeof(double) * h->m.r);
+  return MDS_OK;
+}
+
+mds_status mds_get_landmark_coords(const mds_model* h, double* X1) {
+  if (!h || !X1) return set_error(MDS_ERR_INVALID_ARG, "NULL argument");
+  std::memcpy(X1, h->m.x1_host, sizeof(double) * h->m.l * h->m.r);
+  return MDS_OK;
+}
+
+mds_status mds_get_q(const mds_model* h, double* q) {
+  if (!h || !q) return set_error(MDS_ERR_INVALID_ARG, "NULL argument");
+  std::memcpy(q, h->m.q_host, sizeof(double) * h->m.l);
+  return MDS_OK;
+}
+
+int64_t mds_model_bytes(const mds_model* h) { return h ? h->m.bytes : 0; }
+
+mds_status mds_fit_stats(const mds_model* h, int32_t* steps, int32_t* restarts) {
+  if (!h) return set_error(MDS_ERR_INVALID_ARG, "model is NULL");
+  if (steps) *steps = h->m.lanczos_steps;
+  if (restarts) *restarts = h->m.restarts;
+  return MDS_OK;
+}
+
+}  // extern "C"
+
+// Internal accessor used by the serving layer.
+namespace mds {
+const Model* model_of(const mds_model* h) { return h ? &h->m : nullptr; }
+}  // namespace mds

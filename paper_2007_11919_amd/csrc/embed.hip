@@ -1,0 +1,607 @@
+// Embed: Gower's interpolation formula, eq. (2) of Section 3.1, as one
+// fused kernel.  For a data row x and landmark j
+//     d_j = |x|^2 + |m_j|^2 - 2 x.m_j          (squared distance, Section 2)
+//     e_j = q_j - d_j = c_j - |x|^2 + 2 x.m_j  (c = q - |m|^2, fixed at fit)
+//     y   = sum_j e_j W_j,   W = 1/2 V Lambda^{-1/2}
+// which is eq. (2) with (1/l) X1 S1^{-1} = V Lambda^{-1/2} (Section 3.1).
+// The n x l block of distances never leaves registers.
+//
+// Work decomposition (flash-attention shaped): a 256-thread block owns
+// BM = 128 data rows and walks the landmarks BN = 128 at a time.  Four waves
+// split the 128 x 128 tile into 2 x 2 quadrants of 64 rows x 64 landmarks.
+// The contraction over p is staged through LDS in chunks of 128 bytes per
+// row (double-buffered, one barrier per chunk):
+//   FP32        32 values, v_mfma_f32_16x16x4_f32
+//   FP64        16 values, v_mfma_f64_16x16x4_f64
+//   split BF16  32 hi + 32 lo values, v_mfma_f32_16x16x32_bf16, three
+//               products hi.hi + hi.lo + lo.hi with FP32 accumulation
+//   split FP16  the same with FP16 operands scaled by a power of two
+// The MFMA computes S^T (landmarks x rows), so its accumulator is directly
+// the B operand of the projection MFMA Y^T += W^T E^T (no data movement);
+// the epilogue e = c - |x|^2 + 2 S runs in between on the accumulator.
+// The per-row reduction order is fixed (landmark tiles in order, then the
+// two landmark halves of a block in order), so a row's result does not
+// depend on the batch it arrives in.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "mds_internal.h"
+
+namespace mds {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+
+constexpr int ROW_BYTES = CHUNK_BYTES + 16;  // LDS row stride (16-byte pad)
+constexpr int TILE_BYTES = BM * ROW_BYTES;
+constexpr int LDS_BYTES = 4 * TILE_BYTES + BM * 8;
+
+template <int MODE>
+struct Tr {
+  using T = float;   // epilogue / projection type
+  using Acc = f4;
+  static constexpr int E = 4;          // data elements per 16-byte segment
+  static constexpr int KB = 2;         // MFMA k-blocks per chunk
+  static constexpr int KBLK = 16;      // data elements per k-block
+  static constexpr int CH = 32;        // data elements per chunk
+};
+template <>
+struct Tr<MODE_F64> {
+  using T = double;
+  using Acc = d4;
+  static constexpr int E = 2;
+  static constexpr int KB = 2;
+  static constexpr int KBLK = 8;
+  static constexpr int CH = 16;
+};
+template <>
+struct Tr<MODE_BF16> {
+  using T = float;
+  using Acc = f4;
+  static constexpr int E = 4;
+  static constexpr int KB = 1;
+  static constexpr int KBLK = 32;
+  static constexpr int CH = 32;
+};
+template <>
+struct Tr<MODE_F16> : Tr<MODE_BF16> {};
+
+// Row (within a 16-row MFMA block) held by accumulator element v of a lane
+// in lane group g: the FP64 instruction interleaves rows, the others block.
+template <int MODE>
+__device__ constexpr int acc_row(int g, int v) {
+  return MODE == MODE_F64 ? g + 4 * v : 4 * g + v;
+}
+
+__device__ inline f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename TX, int E>
+struct Seg {
+  TX v[E];
+};
+
+template <typename TX, int E>
+__device__ inline Seg<TX, E> load_seg(const TX* __restrict__ rowp, int64_t k, int p, bool vec) {
+  Seg<TX, E> s;
+  if (vec && k + E <= p) {
+    if constexpr (sizeof(TX) * E == 16) {
+      const u4 raw = *reinterpret_cast<const u4*>(rowp + k);
+      __builtin_memcpy(&s, &raw, 16);
+    } else {
+      const u2 raw = *reinterpret_cast<const u2*>(rowp + k);
+      __builtin_memcpy(&s, &raw, 8);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i) s.v[i] = (k + i < p) ? rowp[k + i] : (TX)0;
+  }
+  return s;
+}
+
+// One 128-row tile of data rows through every landmark tile.
+//   rb_rt: 16-wide output column blocks actually used (<= RB)
+template <int MODE, typename TX, int RB>
+__device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, int64_t ldx,
+                           int nrows, void* __restrict__ Yv, int64_t ldy, char* lds) {
+  using Tt = Tr<MODE>;
+  using T = typename Tt::T;
+  using Acc = typename Tt::Acc;
+  constexpr int E = Tt::E;
+  constexpr bool SPLIT = (MODE == MODE_BF16 || MODE == MODE_F16);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1;   // 64-row half
+  const int wn = wave >> 1;  // 64-landmark half
+  const int lr = lane & 15;
+  const int lg = lane >> 4;
+  const int p = mv.p;
+  const int nch = mv.nchunks;
+  const int ntl = mv.ntl;
+  const int total = nch * ntl;
+  const int rb_rt = mv.rb < RB ? mv.rb : RB;
+  const int ldw = 16 * mv.rb;
+  const bool xvec = ((((uintptr_t)X) & 15) == 0) && ((ldx * (int64_t)sizeof(TX)) % 16 == 0);
+
+  char* Xs = lds;
+  char* Ms = lds + 2 * TILE_BYTES;
+  T* xnorm = reinterpret_cast<T*>(lds + 4 * TILE_BYTES);
+
+  // loader mapping: segment u covers row (tid >> 3) + 32 u, 16-byte slot tid & 7
+  const int lrow = tid >> 3;
+  const int lseg = tid & 7;
+
+  Acc acc[4][4];
+  Acc yacc[4][RB];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < RB; ++b) yacc[a][b] = Acc{0, 0, 0, 0};
+  }
+  T nacc[4] = {0, 0, 0, 0};
+  T xn[4] = {0, 0, 0, 0};
+  Seg<TX, E> xr[4];
+  u4 mr[4];
+  int xlo_cur = 1;  // lo parts of the data chunk being computed are not all zero
+
+  const char* mbase = reinterpret_cast<const char*>(mv.mpack);
+  const T* cvec = reinterpret_cast<const T*>(mv.c);
+  const T* wmat = reinterpret_cast<const T*>(mv.w);
+
+  auto load_chunk = [&](int lt, int ch) {
+    const int64_t k0 = (int64_t)ch * Tt::CH + lseg * E;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = lrow + 32 * u;
+      if (row < nrows) {
+        xr[u] = load_seg<TX, E>(X + (int64_t)row * ldx, k0, p, xvec);
+      } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) xr[u].v[i] = (TX)0;
+      }
+      const int64_t lm = (int64_t)lt * BN + row;
+      mr[u] = *reinterpret_cast<const u4*>(mbase + (lm * nch + ch) * CHUNK_BYTES + lseg * 16);
+    }
+  };
+  auto accumulate_norm = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const T x = (T)xr[u].v[i];
+        nacc[u] = fma(x, x, nacc[u]);
+      }
+  };
+  // returns 1 if any lo part of this thread's data is nonzero (split modes)
+  auto store_chunk = [&](int buf) -> int {
+    int lo_nz = 0;
+    char* xb = Xs + buf * TILE_BYTES;
+    char* mb = Ms + buf * TILE_BYTES;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = lrow + 32 * u;
+      if constexpr (MODE == MODE_F32) {
+        f4 v = {(float)xr[u].v[0], (float)xr[u].v[1], (float)xr[u].v[2], (float)xr[u].v[3]};
+        *reinterpret_cast<f4*>(xb + row * ROW_BYTES + lseg * 16) = v;
+      } else if constexpr (MODE == MODE_F64) {
+        d2 v = {(double)xr[u].v[0], (double)xr[u].v[1]};
+        *reinterpret_cast<d2*>(xb + row * ROW_BYTES + lseg * 16) = v;
+      } else {
+        uint16_t hi[4], lo[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float x = (float)xr[u].v[i];
+          if constexpr (MODE == MODE_BF16) {
+            const __bf16 h = (__bf16)x;
+            const __bf16 lw = (__bf16)(x - (float)h);
+            hi[i] = __builtin_bit_cast(uint16_t, h);
+            lo[i] = __builtin_bit_cast(uint16_t, lw);
+            lo_nz |= ((float)lw != 0.0f);
+          } else {
+            x *= mv.prescale;
+            const _Float16 h = (_Float16)x;
+            const _Float16 lw = (_Float16)(x - (float)h);
+            hi[i] = __builtin_bit_cast(uint16_t, h);
+            lo[i] = __builtin_bit_cast(uint16_t, lw);
+            lo_nz |= ((float)lw != 0.0f);
+          }
+        }
+        u2 hv = {(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
+        u2 lv = {(uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
+        *reinterpret_cast<u2*>(xb + row * ROW_BYTES + lseg * 8) = hv;
+        *reinterpret_cast<u2*>(xb + row * ROW_BYTES + 64 + lseg * 8) = lv;
+      }
+      *reinterpret_cast<u4*>(mb + row * ROW_BYTES + lseg * 16) = mr[u];
+    }
+    return lo_nz;
+  };
+
+  auto compute_chunk = [&](int buf, int ch, bool do_xlo) {
+    const char* xb = Xs + buf * TILE_BYTES;
+    const char* mb = Ms + buf * TILE_BYTES;
+    if constexpr (!SPLIT) {
+#pragma unroll
+      for (int kb = 0; kb < Tt::KB; ++kb) {
+        if (ch * Tt::CH + kb * Tt::KBLK >= p) break;
+        using V = typename std::conditional<MODE == MODE_F64, d2, f4>::type;
+        V a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = *reinterpret_cast<const V*>(mb + (64 * wn + 16 * i + lr) * ROW_BYTES + kb * 64 + lg * 16);
+          b[i] = *reinterpret_cast<const V*>(xb + (64 * wm + 16 * i + lr) * ROW_BYTES + kb * 64 + lg * 16);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 16 / (int)sizeof(T); ++jj)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i][jj], b[j][jj], acc[i][j]);
+      }
+    } else {
+      using V = typename std::conditional<MODE == MODE_BF16, bf8, h8>::type;
+      V ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const char* ma = mb + (64 * wn + 16 * i + lr) * ROW_BYTES + lg * 16;
+        const char* xa = xb + (64 * wm + 16 * i + lr) * ROW_BYTES + lg * 16;
+        ah[i] = *reinterpret_cast<const V*>(ma);
+        al[i] = *reinterpret_cast<const V*>(ma + 64);
+        bh[i] = *reinterpret_cast<const V*>(xa);
+        bl[i] = *reinterpret_cast<const V*>(xa + 64);
+      }
+      const bool do_mlo = !mv.m_lo_zero;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if constexpr (MODE == MODE_BF16) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          } else {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          }
+        }
+    }
+  };
+
+  // epilogue e = c - |x|^2 + 2 s and projection Y^T += W^T E^T for tile lt
+  auto epilogue = [&](int lt) {
+    const int64_t lbase = (int64_t)lt * BN + 64 * wn;
+    const T two = SPLIT ? (T)(2.0f * mv.postscale) : (T)2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      T cv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cv[v] = cvec[lbase + 16 * i + acc_row<MODE>(lg, v)];
+      Acc e[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) e[j][v] = (cv[v] - xn[j]) + two * acc[i][j][v];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb < rb_rt) {
+          T wv[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            wv[v] = wmat[(lbase + 16 * i + acc_row<MODE>(lg, v)) * ldw + 16 * rb + lr];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) yacc[j][rb] = mfma(wv[v], e[j][v], yacc[j][rb]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+    }
+  };
+
+  // ---- pipeline over (landmark tile, chunk) ----
+  load_chunk(0, 0);
+  accumulate_norm();
+  {
+    const int nz = store_chunk(0);
+    xlo_cur = __syncthreads_or(nz);
+  }
+  for (int it = 0; it < total; ++it) {
+    const int buf = it & 1;
+    const int lt = it / nch;
+    const int ch = it - lt * nch;
+    const bool has_next = it + 1 < total;
+    int nlt = 0, nchn = 0;
+    if (has_next) {
+      nlt = (it + 1) / nch;
+      nchn = (it + 1) - nlt * nch;
+      load_chunk(nlt, nchn);
+    }
+    compute_chunk(buf, ch, xlo_cur != 0);
+    int nz = 0;
+    if (has_next) {
+      if (nlt == 0) accumulate_norm();
+      nz = store_chunk(buf ^ 1);
+    }
+    const bool tile_end = (ch == nch - 1);
+    if (tile_end && lt == 0) {
+      // row norms: 8 lanes share each row; fixed butterfly order
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        T s = nacc[u];
+        s += __shfl_xor(s, 4, 64);
+        s += __shfl_xor(s, 2, 64);
+        s += __shfl_xor(s, 1, 64);
+        if (lseg == 0) xnorm[lrow + 32 * u] = s;
+      }
+    }
+    xlo_cur = __syncthreads_or(nz);
+    if (tile_end) {
+      if (lt == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xn[j] = xnorm[64 * wm + 16 * j + lr];
+      }
+      epilogue(lt);
+    }
+  }
+
+  // ---- combine the two landmark halves (fixed order) and store ----
+  __syncthreads();
+  T* ysh = reinterpret_cast<T*>(lds);
+  if (wn == 1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ysh[(((wm * 4 + j) * RB + rb) * 4 + v) * 64 + lane] = yacc[j][rb][v];
+  }
+  __syncthreads();
+  if (wn == 0) {
+    T* Y = reinterpret_cast<T*>(Yv);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 64 * wm + 16 * j + lr;
+      if (row >= nrows) continue;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= rb_rt) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * rb + acc_row<MODE>(lg, v);
+          const T val = yacc[j][rb][v] + ysh[(((wm * 4 + j) * RB + rb) * 4 + v) * 64 + lane];
+          if (col < mv.r) Y[(int64_t)row * ldy + col] = val;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int MODE, typename TX, int RB>
+__global__ __launch_bounds__(THREADS) void k_embed(EmbedModelView mv, const TX* __restrict__ X,
+                                                   int64_t n, int64_t ldx, void* __restrict__ Y,
+                                                   int64_t ldy) {
+  extern __shared__ __align__(16) char lds[];
+  using T = typename Tr<MODE>::T;
+  const int64_t ntiles = (n + BM - 1) / BM;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * BM;
+    const int nrows = (int)((n - row0) < BM ? (n - row0) : BM);
+    embed_tile<MODE, TX, RB>(mv, X + row0 * ldx, ldx, nrows,
+                             reinterpret_cast<T*>(Y) + row0 * ldy, ldy, lds);
+  }
+}
+
+// Persistent serving kernel: blocks stride over a device table of tiles,
+// each naming its model; every tile runs the same embed_tile code as the
+// plain kernel, so results are identical alone and in a mix.
+template <int MODE>
+__global__ __launch_bounds__(THREADS) void k_embed_work(const EmbedModelView* __restrict__ views,
+                                                       const TileWork* __restrict__ work,
+                                                       const int32_t* __restrict__ nwork) {
+  extern __shared__ __align__(16) char lds[];
+  using T = typename Tr<MODE>::T;
+  const int nw = nwork[0];
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+    const TileWork tw = work[w];
+    const EmbedModelView mv = views[tw.model];
+    const float* X = reinterpret_cast<const float*>(tw.x) + tw.row0 * tw.ldx;
+    T* Y = reinterpret_cast<T*>(tw.y) + tw.row0 * tw.ldy;
+    if (mv.rb <= 1)
+      embed_tile<MODE, float, 1>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+    else if (mv.rb == 2)
+      embed_tile<MODE, float, 2>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+    else
+      embed_tile<MODE, float, 4>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+  }
+}
+
+int g_num_cu = 0;
+
+int num_cu() {
+  if (g_num_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+    g_num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  }
+  return g_num_cu;
+}
+
+template <int MODE, typename TX, int RB>
+hipError_t launch_t(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
+                    int64_t ldy, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed<MODE, TX, RB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int64_t ntiles = (n + BM - 1) / BM;
+  const int64_t cap = (int64_t)num_cu() * 2 * 64;
+  const int grid = (int)(ntiles < cap ? ntiles : cap);
+  k_embed<MODE, TX, RB><<<grid, THREADS, LDS_BYTES, st>>>(mv, reinterpret_cast<const TX*>(X), n, ldx,
+                                                           Y, ldy);
+  return hipGetLastError();
+}
+
+template <int MODE, typename TX>
+hipError_t launch_rb(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
+                     int64_t ldy, hipStream_t st) {
+  if (mv.rb <= 1) return launch_t<MODE, TX, 1>(mv, X, n, ldx, Y, ldy, st);
+  if (mv.rb == 2) return launch_t<MODE, TX, 2>(mv, X, n, ldx, Y, ldy, st);
+  return launch_t<MODE, TX, 4>(mv, X, n, ldx, Y, ldy, st);
+}
+
+}  // namespace
+
+int embed_max_rb() { return 4; }
+
+EmbedModelView Model::view(int mode) const {
+  EmbedModelView v{};
+  v.p = (int)p;
+  v.ntl = (int)(l_pad / BN);
+  v.r = r;
+  v.rb = rb;
+  v.prescale = 1.f;
+  v.postscale = 1.f;
+  switch (mode) {
+    case MODE_F64:
+      v.mpack = m64;
+      v.w = w64;
+      v.c = c64;
+      v.nchunks = (int)((p + 15) / 16);
+      break;
+    case MODE_F32:
+      v.mpack = m32;
+      v.w = w32;
+      v.c = c32;
+      v.nchunks = (int)((p + 31) / 32);
+      break;
+    case MODE_BF16:
+      v.mpack = mbf;
+      v.w = w32;
+      v.c = c32;
+      v.nchunks = (int)((p + 31) / 32);
+      v.m_lo_zero = bf_lo_zero;
+      break;
+    default:
+      v.mpack = mh;
+      v.w = w32;
+      v.c = c32;
+      v.nchunks = (int)((p + 31) / 32);
+      v.m_lo_zero = h_lo_zero;
+      v.prescale = h_prescale;
+      v.postscale = h_postscale;
+      break;
+  }
+  return v;
+}
+
+mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t n, int64_t ldx,
+                        void* Y, int64_t ldy, hipStream_t st) {
+  const EmbedModelView mv = m.view(mode);
+  hipError_t e;
+  switch (mode) {
+    case MODE_F64:
+      e = (dt == MDS_F64) ? launch_rb<MODE_F64, double>(mv, X, n, ldx, Y, ldy, st)
+                          : launch_rb<MODE_F64, float>(mv, X, n, ldx, Y, ldy, st);
+      break;
+    case MODE_F32:
+      e = launch_rb<MODE_F32, float>(mv, X, n, ldx, Y, ldy, st);
+      break;
+    case MODE_BF16:
+      e = launch_rb<MODE_BF16, float>(mv, X, n, ldx, Y, ldy, st);
+      break;
+    default:
+      e = launch_rb<MODE_F16, float>(mv, X, n, ldx, Y, ldy, st);
+      break;
+  }
+  if (e != hipSuccess) return hip_fail(e, "embed launch");
+  return MDS_OK;
+}
+
+namespace {
+const void* worklist_fn(int mode) {
+  switch (mode) {
+    case MODE_F32: return reinterpret_cast<const void*>(&k_embed_work<MODE_F32>);
+    case MODE_BF16: return reinterpret_cast<const void*>(&k_embed_work<MODE_BF16>);
+    case MODE_F16: return reinterpret_cast<const void*>(&k_embed_work<MODE_F16>);
+    default: return nullptr;
+  }
+}
+bool g_work_attr[4] = {false, false, false, false};
+}  // namespace
+
+// Sets the kernel's LDS limit outside any stream capture.
+mds_status prepare_embed_worklist(int mode) {
+  const void* fn = worklist_fn(mode);
+  if (!fn) return set_error(MDS_ERR_INVALID_ARG, "serving supports FP32 and split precisions");
+  if (!g_work_attr[mode]) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    g_work_attr[mode] = true;
+  }
+  return MDS_OK;
+}
+
+mds_status launch_embed_worklist(int mode, const EmbedModelView* views_dev, const TileWork* work_dev,
+                                 const int32_t* nwork_dev, int grid, hipStream_t st) {
+  bool* attr_set = g_work_attr;
+  const void* fn = nullptr;
+  switch (mode) {
+    case MODE_F32:
+      fn = reinterpret_cast<const void*>(&k_embed_work<MODE_F32>);
+      break;
+    case MODE_BF16:
+      fn = reinterpret_cast<const void*>(&k_embed_work<MODE_BF16>);
+      break;
+    case MODE_F16:
+      fn = reinterpret_cast<const void*>(&k_embed_work<MODE_F16>);
+      break;
+    default:
+      return set_error(MDS_ERR_INVALID_ARG, "serving supports FP32 and split precisions");
+  }
+  if (!attr_set[mode]) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+    attr_set[mode] = true;
+  }
+  if (grid <= 0) grid = num_cu() * 2;
+  switch (mode) {
+    case MODE_F32:
+      k_embed_work<MODE_F32><<<grid, THREADS, LDS_BYTES, st>>>(views_dev, work_dev, nwork_dev);
+      break;
+    case MODE_BF16:
+      k_embed_work<MODE_BF16><<<grid, THREADS, LDS_BYTES, st>>>(views_dev, work_dev, nwork_dev);
+      break;
+    default:
+      k_embed_work<MODE_F16><<<grid, THREADS, LDS_BYTES, st>>>(views_dev, work_dev, nwork_dev);
+      break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "serving launch");
+  return MDS_OK;
+}
+
+}  // namespace mds

@@ -1,0 +1,109 @@
+// Internal declarations shared by the host sources and the HIP kernels of
+// libmds.  Nothing here is part of the C ABI (see include/mds.h).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mds.h"
+
+namespace mds {
+
+// ---- tiling constants of the fused embed kernel ------------------------
+// A block owns BM data rows and walks the landmarks BN at a time; the
+// contraction over p is staged through LDS in chunks of CHUNK_BYTES per
+// row (32 FP32, 16 FP64, or 32 hi + 32 lo 16-bit values).
+constexpr int BM = 128;
+constexpr int BN = 128;
+constexpr int CHUNK_BYTES = 128;
+constexpr int THREADS = 256;
+
+enum Mode { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16 = 2, MODE_F16 = 3 };
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// elements of the contraction per chunk in each mode
+inline int chunk_elems(int mode) { return mode == MODE_F64 ? 16 : 32; }
+
+// Device-side view of one model for one precision, passed by value.
+struct EmbedModelView {
+  const void* mpack;   // l_pad rows x nchunks x CHUNK_BYTES landmark operands
+  const void* w;       // l_pad x (16*rb) projection weights (float or double)
+  const void* c;       // l_pad: q - |m|^2 (float or double)
+  int p;               // data dimension
+  int nchunks;         // ceil(p / chunk_elems)
+  int ntl;             // l_pad / BN landmark tiles
+  int r;               // output columns written
+  int rb;              // 16-wide blocks of output columns (1..4)
+  int m_lo_zero;       // split modes: every landmark lo part is zero
+  float prescale;      // split FP16: data scaled by 2^s before splitting
+  float postscale;     // split FP16: 2^-2s applied to the dot products
+};
+
+// One row tile of one request, for the persistent serving kernel.
+struct TileWork {
+  const void* x;
+  void* y;
+  int64_t ldx;
+  int64_t ldy;
+  int64_t row0;
+  int32_t nrows;       // rows of this tile (<= BM)
+  int32_t model;       // index into the model-view table
+};
+
+struct Model {
+  int64_t n_fit = 0, p = 0, l = 0, l_pad = 0;
+  int32_t r = 0, r_eff = 0, rb = 1;
+  int dev = 0;
+  int32_t lanczos_steps = 0, restarts = 0;
+  // host copies
+  int64_t* idx_host = nullptr;
+  double* lam_host = nullptr;   // r
+  double* x1_host = nullptr;    // l x r
+  double* q_host = nullptr;     // l
+  // device buffers
+  void* m64 = nullptr;    // l_pad x nchunks64 x 16 doubles (FP64 operand and fit input)
+  void* m32 = nullptr;    // l_pad x nchunks32 x 32 floats
+  void* mbf = nullptr;    // l_pad x nchunks32 x (32 hi + 32 lo) bf16
+  void* mh = nullptr;     // same for FP16 (scaled)
+  void* w32 = nullptr;    // l_pad x 16rb float
+  void* w64 = nullptr;    // l_pad x 16rb double
+  void* c32 = nullptr;    // l_pad float
+  void* c64 = nullptr;    // l_pad double
+  int bf_lo_zero = 0, h_lo_zero = 0;
+  float h_prescale = 1.f, h_postscale = 1.f;
+  int64_t bytes = 0;
+
+  EmbedModelView view(int mode) const;
+};
+
+// ---- error plumbing -----------------------------------------------------
+mds_status set_error(mds_status st, const std::string& msg);
+mds_status hip_fail(hipError_t e, const char* what);
+#define MDS_HIP(call)                                                  \
+  do {                                                                 \
+    hipError_t _e = (call);                                            \
+    if (_e != hipSuccess) return ::mds::hip_fail(_e, #call);           \
+  } while (0)
+
+// ---- host sampler (sampler.cpp) -----------------------------------------
+void sample_landmarks_host(int64_t n, int64_t l, uint64_t seed, int64_t* out);
+
+// ---- fit kernels (fit.hip) ------------------------------------------------
+struct FitScratch;
+mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int64_t* idx_dev,
+                         hipStream_t st);
+
+// ---- embed kernels (embed.hip) -----------------------------------------
+mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t n, int64_t ldx,
+                        void* Y, int64_t ldy, hipStream_t st);
+// persistent serving launch over a device table of tiles
+mds_status launch_embed_worklist(int mode, const EmbedModelView* views_dev,
+                                 const TileWork* work_dev, const int32_t* nwork_dev,
+                                 int grid, hipStream_t st);
+int embed_max_rb();
+mds_status prepare_embed_worklist(int mode);
+
+}  // namespace mds

@@ -1,0 +1,107 @@
+"""The C ABI library on the host: it loads, exports every declared symbol,
+its sampler matches the oracle's vectors bit for bit, and argument checks
+that need no GPU return the documented status codes."""
+
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mds.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "sampler_vectors.json")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2007_11919_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2007_11919_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mds_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ("mds_fit_landmarks", "mds_embed", "mds_free", "mds_sample_landmarks",
+                     "mds_serve_create", "mds_serve_submit", "mds_serve_destroy"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in declared_symbols() if not hasattr(L, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_sampler_matches_oracle_vectors(L):
+    from paper_2007_11919_amd import sample_landmarks
+    ref = json.load(open(GOLDEN))
+    for case in ref["sample_landmarks"]:
+        got = sample_landmarks(case["n"], case["l"], int(case["seed"]))
+        assert got.tolist() == case["idx"], case["n"]
+
+
+def test_bounded_draw_matches_oracle_vectors(L):
+    ref = json.load(open(GOLDEN))
+    for case in ref["bounded"]:
+        out = (ctypes.c_uint64 * 20)()
+        L.mds_debug_bounded(int(case["seed"]), int(case["k"]), 20, out)
+        assert [str(v) for v in out] == case["draws"]
+
+
+def test_sampler_against_oracle_random_cases(L):
+    import oracle
+    from paper_2007_11919_amd import sample_landmarks
+    rng = np.random.Generator(np.random.PCG64(5))
+    for _ in range(40):
+        n = int(rng.integers(1, 10**7))
+        l = int(rng.integers(1, min(n, 3000) + 1))
+        seed = int(rng.integers(0, 2**63))
+        assert sample_landmarks(n, l, seed).tolist() == oracle.sample_landmarks(n, l, seed)
+
+
+def test_sampler_argument_errors(L):
+    out = np.empty(4, dtype=np.int64)
+    P = ctypes.POINTER(ctypes.c_int64)
+    assert L.mds_sample_landmarks(10, 0, 1, out.ctypes.data_as(P)) == 1
+    assert L.mds_sample_landmarks(3, 4, 1, out.ctypes.data_as(P)) == 1
+    assert L.mds_sample_landmarks(10, 2, 1, None) == 1
+    assert b"NULL" in L.mds_last_error()
+
+
+def test_fit_and_embed_argument_errors_need_no_gpu(L):
+    model = ctypes.c_void_p()
+    # NULL X, bad sizes: rejected before any device work
+    assert L.mds_fit_landmarks(None, 0, 100, 4, 4, 10, 2, 0, None, None, ctypes.byref(model)) == 1
+    fake = ctypes.c_void_p(16)
+    assert L.mds_fit_landmarks(fake, 0, 100, 4, 3, 10, 2, 0, None, None, ctypes.byref(model)) == 1
+    assert L.mds_fit_landmarks(fake, 0, 100, 4, 4, 1, 1, 0, None, None, ctypes.byref(model)) == 1
+    assert L.mds_fit_landmarks(fake, 0, 100, 4, 4, 10, 10, 0, None, None, ctypes.byref(model)) == 1
+    assert L.mds_fit_landmarks(fake, 7, 100, 4, 4, 10, 2, 0, None, None, ctypes.byref(model)) == 1
+    assert L.mds_fit_landmarks(fake, 0, 100, 4, 4, 200, 2, 0, None, None, ctypes.byref(model)) == 1
+    dup = (ctypes.c_int64 * 3)(1, 5, 5)
+    assert L.mds_fit_landmarks(fake, 0, 100, 4, 4, 3, 2, 0, dup, None, ctypes.byref(model)) == 1
+    oob = (ctypes.c_int64 * 3)(1, 5, 100)
+    assert L.mds_fit_landmarks(fake, 0, 100, 4, 4, 3, 2, 0, oob, None, ctypes.byref(model)) == 1
+    assert model.value is None
+    assert L.mds_embed(None, fake, 0, 10, 4, 1, fake, 2, None) == 1
+    L.mds_free(None)  # no-op
+
+
+def test_serve_argument_errors_need_no_gpu(L):
+    srv = ctypes.c_void_p()
+    assert L.mds_serve_create(0, 4, 0, ctypes.byref(srv)) == 1
+    assert L.mds_serve_create(1 << 30, 0, 0, ctypes.byref(srv)) == 1
+    assert L.mds_serve_create(1 << 30, 4, -1, ctypes.byref(srv)) == 1
+    t = ctypes.c_int64()
+    assert L.mds_serve_submit(None, 0, None, 0, 1, 1, None, 1, ctypes.byref(t)) == 1
+    L.mds_serve_destroy(None)  # no-op
