@@ -1,0 +1,318 @@
+"""Benchmark of interpolation MDS on one MI355X.
+
+A step is one pass of the whole method over one batch: landmark sampling
+and the FP64 fit (gather, squared distances, double centring, Lanczos
+eigenpairs, finalisation) followed by the fused FP32 embed of every row.
+`value` is rows per second over the timed steps, inputs resident in HBM.
+
+Default workload: 1,000,000 x 100 Gaussian rows (first 10 std devs 20 -> 2,
+then 1), l = 1000 landmarks, r = 10.  Also reported on the same data:
+the split-BF16 embed (speed-up and error), the embed kernel's roofline
+fraction, serving latency (p50/p99) at three loads, and the FP64 oracle on
+the host cores (bounded sample).
+
+    python bench.py [--steps K] [--warmup W] [--workload wide|image]
+    python bench.py --only-embed fp32 --iters 20     (for rocprofv3 runs)
+    python bench.py --copy-calib 1073741824           (counter calibration)
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
+PEAK_BF16_MFMA = 2.5e15     # MI355X dense BF16 matrix, FLOP/s
+PEAK_HBM = 8.0e12           # bytes/s
+
+WORKLOADS = {
+    "wide": dict(n=1_000_000, p=100, l=1000, r=10,
+                 desc="interpolation MDS, 1,000,000 x 100 Gaussian rows (std 20..2 on 10 "
+                      "columns, 1 on 90), l=1000 landmarks, r=10; FP64 fit, FP32 embed"),
+    "image": dict(n=1_000_000, p=784, l=2000, r=10,
+                  desc="interpolation MDS, 1,000,000 x 784 integer rows 0..255 from a "
+                       "10-component Gaussian mixture (std 40), l=2000 landmarks, r=10; "
+                       "FP64 fit, FP32 embed"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_data(name):
+    from synth import generators as gen
+    w = WORKLOADS[name]
+    if name == "wide":
+        return gen.wide_gaussian(w["n"], seed=12)
+    return gen.image_mixture(w["n"], p=w["p"], seed=13)
+
+
+def flops_per_point(p, l, r):
+    # distances 2lp, epilogue 3l, projection 2lr, row norm 2p
+    return 2.0 * l * p + 3.0 * l + 2.0 * l * r + 2.0 * p
+
+
+def time_embed(mds, torch, model, Xd, prec, iters):
+    """Average duration of one mds_embed launch, from HIP events recorded on
+    the stream the kernel is launched on (torch's current stream)."""
+    st = torch.cuda.current_stream()
+    Y = mds.embed(model, Xd, prec=prec)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(iters):
+        mds.embed(model, Xd, prec=prec, Y=Y)
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / iters, Y
+
+
+def counters_for(kernel_tag):
+    """Traffic measured by rocprofv3 --pmc for the current kernel source, or
+    None if the source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = open(os.path.join(ROOT, "paper_2007_11919_amd", "csrc", "embed.hip"), "rb").read()
+    if vals.get("embed_hip_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def serving_run(mds, torch, model, Xd, prec, count, seed, budget):
+    """Poisson load at three fractions of the measured saturated capacity."""
+    from paper_2007_11919_amd.serve import Server
+    from synth import generators as gen
+    n = Xd.shape[0]
+    sizes = gen.request_sizes(count, 200_000, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    offs = rng.integers(0, n - sizes + 1)
+    total = int(sizes.sum())
+    Yall = torch.empty((total, model.r), dtype=torch.float32, device=Xd.device)
+    ystart = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    srv = Server(budget_bytes=budget, max_slots=256, tiles_per_step=2048)
+    mid = srv.add_model(model)
+
+    def run(arrivals):
+        tickets = []
+        t0 = srv.now() + 0.002
+        for i in range(count):
+            if arrivals is not None:
+                target = t0 + arrivals[i]
+                while srv.now() < target:
+                    pass
+            s, o, y0 = int(sizes[i]), int(offs[i]), int(ystart[i])
+            tickets.append(srv.submit(mid, Xd[o:o + s], prec, Yall[y0:y0 + s]))
+        for t in tickets:
+            srv.wait(t, timeout=600.0)
+        recs = [srv.poll(t) for t in tickets]
+        done = np.array([r["t_done"] for r in recs])
+        if arrivals is None:
+            start = min(r["t_submit"] for r in recs)
+            return (done.max() - start), None
+        sched = t0 + arrivals
+        lat = done - sched
+        return done.max() - t0, lat
+
+    run(None)  # warm-up
+    makespan, _ = run(None)
+    cap_rps = count / makespan
+    out = {"precision": prec, "requests": count, "mean_points": float(sizes.mean()),
+           "saturated_points_per_s": float(total / makespan),
+           "saturated_requests_per_s": float(cap_rps), "loads": []}
+    for rho in (0.5, 0.8, 0.95):
+        arr = gen.poisson_arrivals(count, rho * cap_rps, seed + 7)
+        span, lat = run(arr)
+        out["loads"].append({
+            "rho": rho, "rate_requests_per_s": float(rho * cap_rps),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "points_per_s": float(total / span)})
+    srv.close()
+    return out
+
+
+def cpu_baseline(name, X, w, sample_rows, Ys_gpu):
+    """The FP64 oracle, as it stands, on the host cores: full fit plus the
+    embed of a bounded sample of rows, scaled to rows per second of a whole
+    pass.  Also returns the GPU results' error on that sample."""
+    import oracle
+    from synth import errors
+    threads = len(os.sched_getaffinity(0))
+    t = time.perf_counter()
+    fit = oracle.fit_landmarks(X, w["l"], w["r"], seed=0)
+    t_fit = time.perf_counter() - t
+    rows = np.sort(np.random.Generator(np.random.PCG64(99)).choice(X.shape[0], sample_rows,
+                                                                   replace=False))
+    t = time.perf_counter()
+    Yo = oracle.interpolate(fit, X[rows])
+    t_emb = time.perf_counter() - t
+    per_row = t_emb / sample_rows
+    whole = t_fit + per_row * X.shape[0]
+    errs = {}
+    for prec, Y in Ys_gpu.items():
+        e = errors.column_errors(Y[rows], Yo)
+        errs[prec] = {k: e[k] for k in ("rms_rel", "maxabs_rms", "frob_rel")}
+    base = {"value": float(X.shape[0] / whole), "unit": "points/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"oracle fit on all {w['l']} landmarks ({t_fit:.2f} s) + embed of "
+                      f"{sample_rows} random rows ({t_emb:.2f} s), scaled to {X.shape[0]} rows",
+            "fit_s": t_fit, "embed_s_per_row": per_row}
+    return base, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="wide")
+    ap.add_argument("--embed-iters", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--only-embed", choices=["fp32", "split_bf16", "split_fp16", "fp64"])
+    ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--copy-calib", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(rows would shard with one broadcast of the model; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2007_11919_amd as mds
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    if args.copy_calib:
+        n = args.copy_calib // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": n * 4, "launches": 5}))
+        return
+
+    w = WORKLOADS[args.workload]
+    log(f"generating {args.workload} data")
+    X = make_data(args.workload)
+    Xd = torch.from_numpy(X).to(dev)
+    torch.cuda.synchronize()
+
+    if args.only_embed:
+        model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
+        Y = mds.embed(model, Xd, prec=args.only_embed)
+        for _ in range(args.iters):
+            mds.embed(model, Xd, prec=args.only_embed, Y=Y)
+        torch.cuda.synchronize()
+        print(json.dumps({"only_embed": args.only_embed, "iters": args.iters}))
+        return
+
+    n = w["n"]
+
+    def step():
+        model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
+        Y = mds.embed(model, Xd, prec="fp32")
+        torch.cuda.synchronize()
+        model.free()
+        return Y
+
+    log("warm-up")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("timed steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_step = total / args.steps * 1e3
+    value = n * args.steps / total
+
+    # fit alone and the embed kernels alone, on one model
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
+    torch.cuda.synchronize()
+    fit_ms = (time.perf_counter() - t) * 1e3
+    fit_stats = model.fit_stats()
+    t32, Y32 = time_embed(mds, torch, model, Xd, "fp32", args.embed_iters)
+    tbf, Ybf = time_embed(mds, torch, model, Xd, "split_bf16", args.embed_iters)
+    t16, Y16 = time_embed(mds, torch, model, Xd, "split_fp16", args.embed_iters)
+    t64, Y64 = time_embed(mds, torch, model, Xd, "fp64", max(3, args.embed_iters // 4))
+    Y64n = Y64.cpu().numpy()
+    from synth import errors
+    err_vs64 = {}
+    for prec, Y in (("fp32", Y32), ("split_bf16", Ybf), ("split_fp16", Y16)):
+        e = errors.column_errors(Y.cpu().numpy(), Y64n)
+        err_vs64[prec] = {k: e[k] for k in ("rms_rel", "maxabs_rms", "frob_rel")}
+
+    fpp = flops_per_point(w["p"], w["l"], w["r"])
+    flops = fpp * n
+    tag = f"embed_fp32_{args.workload}"
+    roof = {"bound": "mfma", "achieved": flops / t32 / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+            "unit": "TFLOP/s", "frac": flops / t32 / PEAK_FP32_MFMA,
+            "traffic": counters_for(tag), "kernel": "k_embed<FP32> (fused distance + projection)",
+            "flops_per_point": fpp, "points_per_launch": n}
+    out = {
+        "metric": "embedded points/s, FP32 vs split-BF16 at stated err; serving p50/p99 latency",
+        "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["desc"], "n": n, "p": w["p"], "l": w["l"], "r": w["r"]},
+        "roofline": roof,
+        "fit_ms": fit_ms, "fit_lanczos_steps": fit_stats["lanczos_steps"],
+        "embed_fp32_ms": t32 * 1e3, "embed_fp32_points_per_s": n / t32,
+        "split_bf16": {"embed_ms": tbf * 1e3, "points_per_s": n / tbf, "speedup_vs_fp32": t32 / tbf,
+                       "algorithmic_tflops": flops / tbf / 1e12,
+                       "frac_of_bf16_peak_algorithmic": flops / tbf / PEAK_BF16_MFMA},
+        "split_fp16": {"embed_ms": t16 * 1e3, "points_per_s": n / t16, "speedup_vs_fp32": t32 / t16},
+        "embed_fp64_ms": t64 * 1e3,
+        "err_vs_gpu_fp64_all_rows": err_vs64,
+        "paper_context": "paper: 18.34 s for n=1e6, 100 columns, l=250, r=10 on one i9-10900K "
+                         "in R (about 54,500 points/s); different l, not a target",
+    }
+    if not args.no_serve:
+        log("serving runs")
+        budget = 8 << 30
+        out["serving"] = {"budget_bytes": budget, "runs": [
+            serving_run(mds, torch, model, Xd, prec, args.serve_requests, 5, budget)
+            for prec in ("fp32", "split_bf16")]}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        base, errs = cpu_baseline(args.workload, X, w, args.cpu_sample,
+                                  {"fp32": Y32.cpu().numpy(), "split_bf16": Ybf.cpu().numpy(),
+                                   "split_fp16": Y16.cpu().numpy(), "fp64": Y64n})
+        out["cpu_baseline"] = base
+        out["err_vs_oracle_sample"] = errs
+    else:
+        out["cpu_baseline"] = None
+    model.free()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
