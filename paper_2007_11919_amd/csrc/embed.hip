@@ -241,46 +241,47 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
       for (int kb = 0; kb < Tt::KB; ++kb) {
         if (ch * Tt::CH + kb * Tt::KBLK >= p) break;
         using V = typename std::conditional<MODE == MODE_F64, d2, f4>::type;
-        V a[4], b[4];
+        V b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          b[j] = *reinterpret_cast<const V*>(xb + (64 * wm + 16 * j + lr) * ROW_BYTES + kb * 64 + lg * 16);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          a[i] = *reinterpret_cast<const V*>(mb + (64 * wn + 16 * i + lr) * ROW_BYTES + kb * 64 + lg * 16);
-          b[i] = *reinterpret_cast<const V*>(xb + (64 * wm + 16 * i + lr) * ROW_BYTES + kb * 64 + lg * 16);
+          const V a = *reinterpret_cast<const V*>(mb + (64 * wn + 16 * i + lr) * ROW_BYTES + kb * 64 + lg * 16);
+#pragma unroll
+          for (int jj = 0; jj < 16 / (int)sizeof(T); ++jj)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[jj], b[j][jj], acc[i][j]);
         }
-#pragma unroll
-        for (int jj = 0; jj < 16 / (int)sizeof(T); ++jj)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i][jj], b[j][jj], acc[i][j]);
       }
     } else {
       using V = typename std::conditional<MODE == MODE_BF16, bf8, h8>::type;
-      V ah[4], al[4], bh[4], bl[4];
+      V bh[4], bl[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const char* ma = mb + (64 * wn + 16 * i + lr) * ROW_BYTES + lg * 16;
-        const char* xa = xb + (64 * wm + 16 * i + lr) * ROW_BYTES + lg * 16;
-        ah[i] = *reinterpret_cast<const V*>(ma);
-        al[i] = *reinterpret_cast<const V*>(ma + 64);
-        bh[i] = *reinterpret_cast<const V*>(xa);
-        bl[i] = *reinterpret_cast<const V*>(xa + 64);
+      for (int j = 0; j < 4; ++j) {
+        const char* xa = xb + (64 * wm + 16 * j + lr) * ROW_BYTES + lg * 16;
+        bh[j] = *reinterpret_cast<const V*>(xa);
+        bl[j] = *reinterpret_cast<const V*>(xa + 64);
       }
       const bool do_mlo = !mv.m_lo_zero;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        const char* ma = mb + (64 * wn + 16 * i + lr) * ROW_BYTES + lg * 16;
+        const V ah = *reinterpret_cast<const V*>(ma);
+        const V al = *reinterpret_cast<const V*>(ma + 64);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if constexpr (MODE == MODE_BF16) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-            if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-            if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+            if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+            if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
           } else {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-            if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
-            if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
+            if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
+            if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc[i][j], 0, 0, 0);
           }
         }
+      }
     }
   };
 
@@ -395,8 +396,15 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
   __syncthreads();
 }
 
+// Two waves per SIMD (two blocks per CU) where the registers fit without
+// spilling; the FP64 and wide-output variants keep one.
+template <int MODE, int RB>
+constexpr int waves_per_simd() {
+  return (MODE != MODE_F64 && (RB == 1 || (RB == 2 && MODE == MODE_F32))) ? 2 : 1;
+}
+
 template <int MODE, typename TX, int RB>
-__global__ __launch_bounds__(THREADS) void k_embed(EmbedModelView mv, const TX* __restrict__ X,
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(waves_per_simd<MODE, RB>(), waves_per_simd<MODE, RB>()))) void k_embed(EmbedModelView mv, const TX* __restrict__ X,
                                                    int64_t n, int64_t ldx, void* __restrict__ Y,
                                                    int64_t ldy) {
   extern __shared__ __align__(16) char lds[];
@@ -412,11 +420,12 @@ __global__ __launch_bounds__(THREADS) void k_embed(EmbedModelView mv, const TX* 
 
 // Persistent serving kernel: blocks stride over a device table of tiles,
 // each naming its model; every tile runs the same embed_tile code as the
-// plain kernel, so results are identical alone and in a mix.
-template <int MODE>
-__global__ __launch_bounds__(THREADS) void k_embed_work(const EmbedModelView* __restrict__ views,
-                                                       const TileWork* __restrict__ work,
-                                                       const int32_t* __restrict__ nwork) {
+// plain kernel (same template arguments), so results are identical alone
+// and in a mix.  One launch serves models of one 16-column block class.
+template <int MODE, int RB>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(waves_per_simd<MODE, RB>(), waves_per_simd<MODE, RB>()))) void k_embed_work(
+    const EmbedModelView* __restrict__ views, const TileWork* __restrict__ work,
+    const int32_t* __restrict__ nwork) {
   extern __shared__ __align__(16) char lds[];
   using T = typename Tr<MODE>::T;
   const int nw = nwork[0];
@@ -425,12 +434,7 @@ __global__ __launch_bounds__(THREADS) void k_embed_work(const EmbedModelView* __
     const EmbedModelView mv = views[tw.model];
     const float* X = reinterpret_cast<const float*>(tw.x) + tw.row0 * tw.ldx;
     T* Y = reinterpret_cast<T*>(tw.y) + tw.row0 * tw.ldy;
-    if (mv.rb <= 1)
-      embed_tile<MODE, float, 1>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
-    else if (mv.rb == 2)
-      embed_tile<MODE, float, 2>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
-    else
-      embed_tile<MODE, float, 4>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+    embed_tile<MODE, float, RB>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
   }
 }
 
@@ -542,62 +546,65 @@ mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t
 }
 
 namespace {
-const void* worklist_fn(int mode) {
+template <int MODE>
+const void* worklist_fn_rb(int rbc) {
+  switch (rbc) {
+    case 0: return reinterpret_cast<const void*>(&k_embed_work<MODE, 1>);
+    case 1: return reinterpret_cast<const void*>(&k_embed_work<MODE, 2>);
+    default: return reinterpret_cast<const void*>(&k_embed_work<MODE, 4>);
+  }
+}
+const void* worklist_fn(int mode, int rbc) {
   switch (mode) {
-    case MODE_F32: return reinterpret_cast<const void*>(&k_embed_work<MODE_F32>);
-    case MODE_BF16: return reinterpret_cast<const void*>(&k_embed_work<MODE_BF16>);
-    case MODE_F16: return reinterpret_cast<const void*>(&k_embed_work<MODE_F16>);
+    case MODE_F32: return worklist_fn_rb<MODE_F32>(rbc);
+    case MODE_BF16: return worklist_fn_rb<MODE_BF16>(rbc);
+    case MODE_F16: return worklist_fn_rb<MODE_F16>(rbc);
     default: return nullptr;
   }
 }
-bool g_work_attr[4] = {false, false, false, false};
+bool g_work_attr[4][3] = {};
+
+template <int MODE>
+void launch_work_rb(int rbc, int grid, hipStream_t st, const EmbedModelView* v, const TileWork* w,
+                    const int32_t* nw) {
+  switch (rbc) {
+    case 0: k_embed_work<MODE, 1><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
+    case 1: k_embed_work<MODE, 2><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
+    default: k_embed_work<MODE, 4><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
+  }
+}
 }  // namespace
 
+int rb_class(int rb) { return rb <= 1 ? 0 : (rb == 2 ? 1 : 2); }
+
+int embed_blocks_per_cu(int mode, int rbc) {
+  if (mode == MODE_F64 || rbc == 2) return 1;
+  if (rbc == 0) return 2;
+  return mode == MODE_F32 ? 2 : 1;
+}
+
 // Sets the kernel's LDS limit outside any stream capture.
-mds_status prepare_embed_worklist(int mode) {
-  const void* fn = worklist_fn(mode);
+mds_status prepare_embed_worklist(int mode, int rbc) {
+  const void* fn = worklist_fn(mode, rbc);
   if (!fn) return set_error(MDS_ERR_INVALID_ARG, "serving supports FP32 and split precisions");
-  if (!g_work_attr[mode]) {
+  if (!g_work_attr[mode][rbc]) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-    g_work_attr[mode] = true;
+    g_work_attr[mode][rbc] = true;
   }
   return MDS_OK;
 }
 
-mds_status launch_embed_worklist(int mode, const EmbedModelView* views_dev, const TileWork* work_dev,
-                                 const int32_t* nwork_dev, int grid, hipStream_t st) {
-  bool* attr_set = g_work_attr;
-  const void* fn = nullptr;
+mds_status launch_embed_worklist(int mode, int rbc, const EmbedModelView* views_dev,
+                                 const TileWork* work_dev, const int32_t* nwork_dev, int grid,
+                                 hipStream_t st) {
+  mds_status s = prepare_embed_worklist(mode, rbc);
+  if (s != MDS_OK) return s;
+  if (grid <= 0) grid = num_cu() * embed_blocks_per_cu(mode, rbc);
   switch (mode) {
-    case MODE_F32:
-      fn = reinterpret_cast<const void*>(&k_embed_work<MODE_F32>);
-      break;
-    case MODE_BF16:
-      fn = reinterpret_cast<const void*>(&k_embed_work<MODE_BF16>);
-      break;
-    case MODE_F16:
-      fn = reinterpret_cast<const void*>(&k_embed_work<MODE_F16>);
-      break;
-    default:
-      return set_error(MDS_ERR_INVALID_ARG, "serving supports FP32 and split precisions");
-  }
-  if (!attr_set[mode]) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
-    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-    attr_set[mode] = true;
-  }
-  if (grid <= 0) grid = num_cu() * 2;
-  switch (mode) {
-    case MODE_F32:
-      k_embed_work<MODE_F32><<<grid, THREADS, LDS_BYTES, st>>>(views_dev, work_dev, nwork_dev);
-      break;
-    case MODE_BF16:
-      k_embed_work<MODE_BF16><<<grid, THREADS, LDS_BYTES, st>>>(views_dev, work_dev, nwork_dev);
-      break;
-    default:
-      k_embed_work<MODE_F16><<<grid, THREADS, LDS_BYTES, st>>>(views_dev, work_dev, nwork_dev);
-      break;
+    case MODE_F32: launch_work_rb<MODE_F32>(rbc, grid, st, views_dev, work_dev, nwork_dev); break;
+    case MODE_BF16: launch_work_rb<MODE_BF16>(rbc, grid, st, views_dev, work_dev, nwork_dev); break;
+    default: launch_work_rb<MODE_F16>(rbc, grid, st, views_dev, work_dev, nwork_dev); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "serving launch");

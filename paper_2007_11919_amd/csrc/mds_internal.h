@@ -100,10 +100,13 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
 mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t n, int64_t ldx,
                         void* Y, int64_t ldy, hipStream_t st);
 // persistent serving launch over a device table of tiles
-mds_status launch_embed_worklist(int mode, const EmbedModelView* views_dev,
+// rbc = rb_class(rb): 0 for rb 1, 1 for rb 2, 2 for rb 3..4
+mds_status launch_embed_worklist(int mode, int rbc, const EmbedModelView* views_dev,
                                  const TileWork* work_dev, const int32_t* nwork_dev,
                                  int grid, hipStream_t st);
 int embed_max_rb();
-mds_status prepare_embed_worklist(int mode);
+int rb_class(int rb);
+int embed_blocks_per_cu(int mode, int rbc);
+mds_status prepare_embed_worklist(int mode, int rbc);
 
 }  // namespace mds

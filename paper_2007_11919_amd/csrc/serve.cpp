@@ -27,7 +27,6 @@
 
 namespace mds {
 const Model* model_of(const mds_model* h);
-mds_status prepare_embed_worklist(int mode);
 }  // namespace mds
 
 using namespace mds;
@@ -36,6 +35,8 @@ namespace {
 
 constexpr int kSlots = 3;          // steps that may be in flight at once
 constexpr int kModes = 3;          // FP32, split BF16, split FP16
+constexpr int kRbc = 3;            // output column-block classes (r <= 16, <= 32, <= 64)
+constexpr int kGraphs = kModes * kRbc;
 constexpr int kMaxModels = 1024;
 constexpr int kDefaultTiles = 2048;
 
@@ -45,6 +46,7 @@ int mode_of_index(int i) { return i == 0 ? MODE_F32 : (i == 1 ? MODE_BF16 : MODE
 struct Request {
   int32_t model = 0;
   int mode = MODE_F32;
+  int rbc = 0;
   const void* x = nullptr;
   void* y = nullptr;
   int64_t n = 0, ldx = 0, ldy = 0;
@@ -63,8 +65,8 @@ struct Slot {
   char* host = nullptr;   // pinned: StepHeader + TileWork[cap]
   char* dev = nullptr;    // device copy
   hipEvent_t done = nullptr;
-  hipGraphExec_t exec[kModes] = {nullptr, nullptr, nullptr};
-  hipGraph_t graph[kModes] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[kGraphs] = {};
+  hipGraph_t graph[kGraphs] = {};
   bool busy = false;
   std::vector<std::pair<int64_t, int64_t>> parts;  // (ticket, tiles in this step)
   int64_t rows = 0;
@@ -158,11 +160,13 @@ void admit_locked(mds_server* s) {
   }
 }
 
-// Fill slot `sl` with tiles of one precision (caller holds the lock).
-// Returns false if there is nothing to run.
-bool build_step_locked(mds_server* s, Slot& sl, int* mode_out) {
+// Fill slot `sl` with tiles of one precision and column-block class, taken
+// from the oldest request onward (caller holds the lock).  Returns false if
+// there is nothing to run.
+bool build_step_locked(mds_server* s, Slot& sl, int* graph_out) {
   if (s->active.empty()) return false;
   const int mode = s->reqs[s->active.front()].mode;
+  const int rbc = s->reqs[s->active.front()].rbc;
   StepHeader* hdr = reinterpret_cast<StepHeader*>(sl.host);
   TileWork* tw = reinterpret_cast<TileWork*>(sl.host + sizeof(StepHeader));
   int nw = 0;
@@ -170,7 +174,7 @@ bool build_step_locked(mds_server* s, Slot& sl, int* mode_out) {
   sl.rows = 0;
   for (size_t a = 0; a < s->active.size() && nw < s->tiles_cap; ++a) {
     Request& rq = s->reqs[s->active[a]];
-    if (rq.mode != mode) continue;
+    if (rq.mode != mode || rq.rbc != rbc) continue;
     int64_t took = 0;
     while (rq.next_tile < rq.ntiles && nw < s->tiles_cap) {
       const int64_t row0 = rq.next_tile * BM;
@@ -196,7 +200,7 @@ bool build_step_locked(mds_server* s, Slot& sl, int* mode_out) {
                                  }),
                   s->active.end());
   hdr->nwork = nw;
-  *mode_out = mode;
+  *graph_out = mode_index(mode) * kRbc + rbc;
   s->stats.steps += 1;
   s->stats.tiles += nw;
   return nw > 0;
@@ -208,12 +212,12 @@ void worker_main(mds_server* s) {
     // retire the slot we are about to reuse
     Slot& sl = s->slots[s->next_slot];
     if (sl.busy) retire(s, sl);
-    int mode = MODE_F32;
+    int gi = 0;
     bool have = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       admit_locked(s);
-      have = build_step_locked(s, sl, &mode);
+      have = build_step_locked(s, sl, &gi);
       if (!have) {
         // nothing new to launch: retire in-flight steps, then sleep
         bool any_busy = false;
@@ -236,7 +240,7 @@ void worker_main(mds_server* s) {
       }
       continue;
     }
-    hipError_t e = hipGraphLaunch(sl.exec[mode_index(mode)], s->stream);
+    hipError_t e = hipGraphLaunch(sl.exec[gi], s->stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, s->stream);
     if (e != hipSuccess) {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -248,13 +252,15 @@ void worker_main(mds_server* s) {
 }
 
 mds_status capture_graphs(mds_server* s) {
-  for (int mi = 0; mi < kModes; ++mi) {
-    mds_status st = prepare_embed_worklist(mode_of_index(mi));
-    if (st != MDS_OK) return st;
-  }
+  for (int mi = 0; mi < kModes; ++mi)
+    for (int rbc = 0; rbc < kRbc; ++rbc) {
+      mds_status st = prepare_embed_worklist(mode_of_index(mi), rbc);
+      if (st != MDS_OK) return st;
+    }
   for (int k = 0; k < kSlots; ++k) {
     Slot& sl = s->slots[k];
-    for (int mi = 0; mi < kModes; ++mi) {
+    for (int gi = 0; gi < kGraphs; ++gi) {
+      const int mi = gi / kRbc, rbc = gi % kRbc;
       MDS_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipMemcpyAsync(sl.dev, sl.host, slot_bytes(s->tiles_cap), hipMemcpyHostToDevice,
                                     s->stream);
@@ -262,7 +268,7 @@ mds_status capture_graphs(mds_server* s) {
       if (e == hipSuccess) {
         const StepHeader* hdr = reinterpret_cast<const StepHeader*>(sl.dev);
         const TileWork* tw = reinterpret_cast<const TileWork*>(sl.dev + sizeof(StepHeader));
-        st = launch_embed_worklist(mode_of_index(mi), s->views_dev[mi], tw, &hdr->nwork, s->grid,
+        st = launch_embed_worklist(mode_of_index(mi), rbc, s->views_dev[mi], tw, &hdr->nwork, 0,
                                    s->stream);
       }
       hipGraph_t g = nullptr;
@@ -270,8 +276,8 @@ mds_status capture_graphs(mds_server* s) {
       if (e != hipSuccess) return hip_fail(e, "capture memcpy");
       if (st != MDS_OK) return st;
       if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-      sl.graph[mi] = g;
-      MDS_HIP(hipGraphInstantiate(&sl.exec[mi], g, nullptr, nullptr, 0));
+      sl.graph[gi] = g;
+      MDS_HIP(hipGraphInstantiate(&sl.exec[gi], g, nullptr, nullptr, 0));
     }
   }
   return MDS_OK;
@@ -279,9 +285,9 @@ mds_status capture_graphs(mds_server* s) {
 
 void destroy_server(mds_server* s) {
   for (auto& sl : s->slots) {
-    for (int mi = 0; mi < kModes; ++mi) {
-      if (sl.exec[mi]) (void)hipGraphExecDestroy(sl.exec[mi]);
-      if (sl.graph[mi]) (void)hipGraphDestroy(sl.graph[mi]);
+    for (int gi = 0; gi < kGraphs; ++gi) {
+      if (sl.exec[gi]) (void)hipGraphExecDestroy(sl.exec[gi]);
+      if (sl.graph[gi]) (void)hipGraphDestroy(sl.graph[gi]);
     }
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.host) (void)hipHostFree(sl.host);
@@ -315,7 +321,7 @@ mds_status mds_serve_create(int64_t budget_bytes, int32_t max_slots, int32_t til
   hipDeviceProp_t prop;
   if (e == hipSuccess && hipGetDeviceProperties(&prop, s->dev) == hipSuccess && prop.multiProcessorCount > 0)
     ncu = prop.multiProcessorCount;
-  s->grid = ncu;  // one block per CU (the kernel runs one 256-thread block per CU)
+  (void)ncu;
   mds_status st = MDS_OK;
   do {
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess) {
@@ -395,6 +401,7 @@ mds_status mds_serve_submit(mds_server* s, int32_t model_id, const void* X, int6
   Request rq;
   rq.model = model_id;
   rq.mode = mode;
+  rq.rbc = rb_class(m->rb);
   rq.x = X;
   rq.y = Y;
   rq.n = n_pts;
