@@ -36,9 +36,7 @@ mds_status hip_fail(hipError_t e, const char* what) {
 namespace {
 
 void free_model(Model& m) {
-  void* bufs[] = {m.m64, m.m32, m.mbf, m.mh, m.w32, m.w64, m.c32, m.c64};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+  if (m.base) (void)hipFree(m.base);
   delete[] m.idx_host;
   delete[] m.lam_host;
   delete[] m.x1_host;

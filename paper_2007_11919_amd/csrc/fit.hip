@@ -176,20 +176,30 @@ __global__ void k_fill_random(double* __restrict__ w, int64_t l, uint64_t salt) 
   if (i < l) w[i] = hash_unit((uint64_t)i, salt);
 }
 
-// w = Q v, one wave per row
+// fixed-order sum over a 256-thread block: butterfly within each wave, then
+// the four wave partials in order
+__device__ inline double block_sum4(double v, double* sh4) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+  __syncthreads();
+  return r;
+}
+
+// w = Q v, one block per row
 __global__ __launch_bounds__(256) void k_symv(const double* __restrict__ Q, int64_t l,
                                               const double* __restrict__ v,
                                               double* __restrict__ w, const int* __restrict__ ctrl) {
   if (ctrl[0]) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= l) return;
+  __shared__ double sh4[4];
+  const int64_t row = blockIdx.x;
   const double* qr = Q + row * l;
   double s = 0.0;
-  for (int64_t c = lane; c < l; c += 64) s = fma(qr[c], v[c], s);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) w[row] = s;
+  for (int64_t c = threadIdx.x; c < l; c += 256) s = fma(qr[c], v[c], s);
+  s = block_sum4(s, sh4);
+  if (threadIdx.x == 0) w[row] = s;
 }
 
 // h_c = V_c' w for c < ncols (one block per column)
@@ -197,28 +207,32 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int6
                                               const double* __restrict__ w, double* __restrict__ h,
                                               const int* __restrict__ ctrl) {
   if (ctrl[0]) return;
-  __shared__ double sh[RED_THREADS];
+  __shared__ double sh4[4];
   const int64_t c = blockIdx.x;
   const double* vc = V + c * l;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < l; i += RED_THREADS) s = fma(vc[i], w[i], s);
-  s = block_sum(s, sh);
+  for (int64_t i = threadIdx.x; i < l; i += 256) s = fma(vc[i], w[i], s);
+  s = block_sum4(s, sh4);
   if (threadIdx.x == 0) h[c] = s;
 }
 
-// w -= V[:, :ncols] h
+// w -= V[:, :ncols] h; a block owns 64 rows, four column groups combined in order
 __global__ __launch_bounds__(256) void k_update(const double* __restrict__ V, int64_t l, int ncols,
                                                 const double* __restrict__ h,
                                                 double* __restrict__ w, const int* __restrict__ ctrl) {
   if (ctrl[0]) return;
   extern __shared__ double hs[];
+  __shared__ double part[4][64];
   for (int c = threadIdx.x; c < ncols; c += blockDim.x) hs[c] = h[c];
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= l) return;
+  const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + rl;
   double s = 0.0;
-  for (int c = 0; c < ncols; ++c) s = fma(V[(int64_t)c * l + i], hs[c], s);
-  w[i] -= s;
+  if (i < l)
+    for (int c = g; c < ncols; c += 4) s = fma(V[(int64_t)c * l + i], hs[c], s);
+  part[g][rl] = s;
+  __syncthreads();
+  if (g == 0 && i < l) w[i] -= ((part[0][rl] + part[1][rl]) + part[2][rl]) + part[3][rl];
 }
 
 // alpha_j, beta_j = |w|, v_{j+1} = w / beta_j, or flag an invariant subspace.
@@ -305,108 +319,58 @@ __device__ int sturm_count(const double* alpha, const double* beta, int k, doubl
   return cnt;
 }
 
-__device__ void tridiag_solve(const double* alpha, const double* beta, int k, double theta,
-                              double pert, double* z, double* dd, double* u1, double* u2,
-                              double* mult, int* piv) {
-  // LU with partial pivoting of T - theta I, then solve in place on z.
-  double cur_d = alpha[0] - theta;
-  double cur_u = (k > 1) ? beta[0] : 0.0;
-  double cur_u2 = 0.0;
-  for (int i = 0; i < k - 1; ++i) {
-    const double sub = beta[i];
-    const double nd = alpha[i + 1] - theta;
-    const double nu = (i + 1 < k - 1) ? beta[i + 1] : 0.0;
-    if (fabs(cur_d) >= fabs(sub)) {
-      double dpiv = cur_d;
-      if (dpiv == 0.0) dpiv = pert;
-      const double mlt = sub / dpiv;
-      dd[i] = dpiv;
-      u1[i] = cur_u;
-      u2[i] = cur_u2;
-      mult[i] = mlt;
-      piv[i] = 0;
-      cur_d = nd - mlt * cur_u;
-      cur_u = nu - mlt * cur_u2;  // cur_u2 feeds column i+2 of row i+1
-      cur_u2 = 0.0;
-    } else {
-      const double mlt = cur_d / sub;
-      dd[i] = sub;
-      u1[i] = nd;
-      u2[i] = nu;
-      mult[i] = mlt;
-      piv[i] = 1;
-      const double nd2 = cur_u - mlt * nd;
-      const double nu2 = cur_u2 - mlt * nu;
-      cur_d = nd2;
-      cur_u = nu2;
-      cur_u2 = 0.0;
-    }
-  }
-  dd[k - 1] = (cur_d == 0.0) ? pert : cur_d;
-  // forward: apply row swaps and multipliers to z
-  for (int i = 0; i < k - 1; ++i) {
-    if (piv[i]) {
-      const double t = z[i];
-      z[i] = z[i + 1];
-      z[i + 1] = t - mult[i] * z[i];
-    } else {
-      z[i + 1] -= mult[i] * z[i];
-    }
-  }
-  // backward with U (diag dd, super u1, second super u2)
-  for (int i = k - 1; i >= 0; --i) {
-    double s = z[i];
-    if (i + 1 < k) s -= u1[i] * z[i + 1];
-    if (i + 2 < k) s -= u2[i] * z[i + 2];
-    double di = dd[i];
-    if (fabs(di) < pert) di = (di < 0 ? -pert : pert);
-    z[i] = s / di;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alpha,
                                                  const double* __restrict__ beta,
                                                  const int* __restrict__ ctrl, int k_host, int r,
                                                  double* __restrict__ theta_out,
                                                  double* __restrict__ bound_out,
                                                  double* __restrict__ S, int ldS,
-                                                 double* __restrict__ work, int* __restrict__ kout) {
+                                                 double* __restrict__ gwork, int* __restrict__ kout,
+                                                 int work_in_lds) {
+  extern __shared__ double sm[];
   __shared__ double sh[256];
-  __shared__ double shx[257];
-  __shared__ int shi[256];
-  __shared__ double theta[MDS_MAX_R];
+  __shared__ double sh4[4];
+  __shared__ double ga[MDS_MAX_R], gb[MDS_MAX_R], theta[MDS_MAX_R];
+  __shared__ int flag[256];
   const int t = threadIdx.x;
   const int k = ctrl[0] ? ctrl[1] + 1 : k_host;
   const int nr = min(r, k);
+  double* al = sm;
+  double* be = sm + k;
+  for (int i = t; i < k; i += 256) {
+    al[i] = alpha[i];
+    be[i] = beta[i];
+  }
+  __syncthreads();
   // Gershgorin interval and scale
   double lo = DBL_MAX, hi = -DBL_MAX, bmax = 0.0;
   for (int i = t; i < k; i += 256) {
-    const double bl = (i > 0) ? fabs(beta[i - 1]) : 0.0;
-    const double br = (i < k - 1) ? fabs(beta[i]) : 0.0;
-    lo = fmin(lo, alpha[i] - bl - br);
-    hi = fmax(hi, alpha[i] + bl + br);
+    const double bl = (i > 0) ? fabs(be[i - 1]) : 0.0;
+    const double br = (i < k - 1) ? fabs(be[i]) : 0.0;
+    lo = fmin(lo, al[i] - bl - br);
+    hi = fmax(hi, al[i] + bl + br);
     bmax = fmax(bmax, br);
   }
   sh[t] = lo;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) sh[t] = fmin(sh[t], sh[t + s]);
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (t < s2) sh[t] = fmin(sh[t], sh[t + s2]);
     __syncthreads();
   }
   lo = sh[0];
   __syncthreads();
   sh[t] = hi;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (t < s2) sh[t] = fmax(sh[t], sh[t + s2]);
     __syncthreads();
   }
   hi = sh[0];
   __syncthreads();
   sh[t] = bmax;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (t < s2) sh[t] = fmax(sh[t], sh[t + s2]);
     __syncthreads();
   }
   bmax = sh[0];
@@ -417,80 +381,143 @@ __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alph
   lo -= 2.0 * eps * tnorm + pivmin;
   hi += 2.0 * eps * tnorm + pivmin;
 
-  // eigenvalues, largest first: index m = k-1-tt in ascending order
-  for (int tt = 0; tt < nr; ++tt) {
-    const int m = k - 1 - tt;
-    double a = lo, b = hi;
-    for (int round = 0; round < 12; ++round) {
-      if (b - a <= 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin) break;
-      const double x = a + (b - a) * (double)(t + 1) / 257.0;
-      shx[t] = x;
-      const int c = sturm_count(alpha, beta, k, x, pivmin);
-      shi[t] = (c >= m + 1) ? t : 256;
-      __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) shi[t] = min(shi[t], shi[t + s]);
-        __syncthreads();
+  // All wanted eigenvalues at once: a group of G threads multisects each.
+  int G = 256;
+  while (G > 1 && G * nr > 256) G >>= 1;
+  const int grp = t / G, gl = t % G;
+  const bool active = grp < nr;
+  if (t < nr) {
+    ga[t] = lo;
+    gb[t] = hi;
+  }
+  __syncthreads();
+  const int m = k - 1 - grp;  // ascending index of eigenvalue grp (largest first)
+  for (int round = 0; round < 64; ++round) {
+    int more = 0;
+    if (active) {
+      const double a = ga[grp], b = gb[grp];
+      more = (b - a > 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin) ? 1 : 0;
+      if (more) {
+        const double x = a + (b - a) * (double)(gl + 1) / (double)(G + 1);
+        flag[t] = sturm_count(al, be, k, x, pivmin) >= m + 1;
       }
-      const int first = shi[0];
-      double na, nb;
-      if (first == 256) {
-        na = shx[255];
-        nb = b;
-      } else {
-        na = (first == 0) ? a : shx[first - 1];
-        nb = shx[first];
-      }
-      __syncthreads();
-      a = na;
-      b = nb;
     }
-    if (t == 0) theta[tt] = 0.5 * (a + b);
+    if (!__syncthreads_or(more)) break;
+    if (active && gl == 0) {
+      const double a = ga[grp], b = gb[grp];
+      if (b - a > 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin) {
+        int first = G;
+        for (int q = 0; q < G; ++q)
+          if (flag[grp * G + q]) {
+            first = q;
+            break;
+          }
+        const double xa = (first == 0) ? a : a + (b - a) * (double)first / (double)(G + 1);
+        const double xb = (first == G) ? b : a + (b - a) * (double)(first + 1) / (double)(G + 1);
+        ga[grp] = xa;
+        gb[grp] = xb;
+      }
+    }
     __syncthreads();
   }
+  if (t < nr) theta[t] = 0.5 * (ga[t] + gb[t]);
+  __syncthreads();
 
   // eigenvectors by inverse iteration (thread tt owns vector tt)
   const double pert = eps * fmax(tnorm, DBL_MIN) + pivmin;
   const double cluster_gap = 1e-3 * tnorm;
+  double* wk = work_in_lds ? (sm + 2 * k) : gwork;  // [4 arrays][k][nr]
   for (int it = 0; it < 3; ++it) {
     if (t < nr) {
       double* z = S + (int64_t)t * ldS;
-      double* dd = work + (int64_t)t * 5 * ldS;
-      double* u1 = dd + ldS;
-      double* u2 = u1 + ldS;
-      double* mult = u2 + ldS;
-      int* piv = (int*)(mult + ldS);
-      if (it == 0)
-        for (int i = 0; i < k; ++i) z[i] = 1.0 + 0.5 * hash_unit((uint64_t)i, 977 + t);
-      tridiag_solve(alpha, beta, k, theta[t], pert, z, dd, u1, u2, mult, piv);
-      double nn = 0.0;
-      for (int i = 0; i < k; ++i) nn = fma(z[i], z[i], nn);
+      const double th = theta[t];
+      // factor T - th I with partial pivoting, applying the row operations to
+      // the right-hand side on the fly; keep U (dd, u1, u2) and the
+      // eliminated right-hand side y for the backward pass.
+      double zc = (it == 0) ? 1.0 + 0.5 * hash_unit(0, 977 + t) : z[0];
+      double cur_d = al[0] - th;
+      double cur_u = (k > 1) ? be[0] : 0.0;
+      double cur_u2 = 0.0;
+      for (int i = 0; i < k - 1; ++i) {
+        const double sub = be[i];
+        const double nd = al[i + 1] - th;
+        const double nu = (i + 1 < k - 1) ? be[i + 1] : 0.0;
+        const double zn = (it == 0) ? 1.0 + 0.5 * hash_unit((uint64_t)(i + 1), 977 + t) : z[i + 1];
+        double di, u1, u2, y;
+        if (fabs(cur_d) >= fabs(sub)) {
+          di = (cur_d == 0.0) ? pert : cur_d;
+          const double mlt = sub / di;
+          u1 = cur_u;
+          u2 = cur_u2;
+          y = zc;
+          zc = zn - mlt * zc;
+          cur_d = nd - mlt * cur_u;
+          cur_u = nu - mlt * cur_u2;
+        } else {
+          const double mlt = cur_d / sub;
+          di = sub;
+          u1 = nd;
+          u2 = nu;
+          y = zn;
+          zc = zc - mlt * zn;
+          const double nd2 = cur_u - mlt * nd;
+          const double nu2 = cur_u2 - mlt * nu;
+          cur_d = nd2;
+          cur_u = nu2;
+        }
+        cur_u2 = 0.0;
+        wk[((int64_t)i * 4 + 0) * nr + t] = di;
+        wk[((int64_t)i * 4 + 1) * nr + t] = u1;
+        wk[((int64_t)i * 4 + 2) * nr + t] = u2;
+        wk[((int64_t)i * 4 + 3) * nr + t] = y;
+      }
+      double dl = (cur_d == 0.0) ? pert : cur_d;
+      if (fabs(dl) < pert) dl = (dl < 0 ? -pert : pert);
+      // backward substitution with a rolling window of two values
+      double z1 = zc / dl, z2 = 0.0;
+      double nn = z1 * z1;
+      z[k - 1] = z1;
+      for (int i = k - 2; i >= 0; --i) {
+        double di = wk[((int64_t)i * 4 + 0) * nr + t];
+        const double u1 = wk[((int64_t)i * 4 + 1) * nr + t];
+        const double u2 = wk[((int64_t)i * 4 + 2) * nr + t];
+        const double y = wk[((int64_t)i * 4 + 3) * nr + t];
+        if (fabs(di) < pert) di = (di < 0 ? -pert : pert);
+        const double zi = (y - u1 * z1 - u2 * z2) / di;
+        z2 = z1;
+        z1 = zi;
+        z[i] = zi;
+        nn = fma(zi, zi, nn);
+      }
       const double inv = 1.0 / sqrt(nn);
       for (int i = 0; i < k; ++i) z[i] *= inv;
     }
     __syncthreads();
     // modified Gram-Schmidt inside clusters of close eigenvalues
     for (int tt = 1; tt < nr; ++tt) {
+      bool any = false;
+      for (int ss = 0; ss < tt; ++ss) any |= fabs(theta[tt] - theta[ss]) <= cluster_gap;
+      if (!any) continue;
       double* zt = S + (int64_t)tt * ldS;
       for (int ss = 0; ss < tt; ++ss) {
         if (fabs(theta[tt] - theta[ss]) > cluster_gap) continue;
         const double* zs = S + (int64_t)ss * ldS;
         double d = 0.0;
         for (int i = t; i < k; i += 256) d = fma(zs[i], zt[i], d);
-        d = block_sum(d, sh);
+        d = block_sum4(d, sh4);
         for (int i = t; i < k; i += 256) zt[i] -= d * zs[i];
         __syncthreads();
       }
       double nn = 0.0;
       for (int i = t; i < k; i += 256) nn = fma(zt[i], zt[i], nn);
-      nn = block_sum(nn, sh);
+      nn = block_sum4(nn, sh4);
       const double inv = 1.0 / sqrt(nn);
       for (int i = t; i < k; i += 256) zt[i] *= inv;
       __syncthreads();
     }
   }
   if (t < nr) {
-    const double coupling = fabs(beta[k - 1]);
+    const double coupling = fabs(be[k - 1 < 0 ? 0 : k - 1]);
     theta_out[t] = theta[t];
     bound_out[t] = coupling * fabs(S[(int64_t)t * ldS + (k - 1)]);
   }
@@ -560,28 +587,59 @@ __global__ __launch_bounds__(256) void k_finalize_cols(double* __restrict__ Vr, 
   }
 }
 
-// c = q - |m|^2 per landmark (zero for padding rows), FP64 and FP32
+// c = q - |m|^2 per landmark (zero for padding rows), FP64 and FP32; also
+// the largest |m| of each landmark row
 __global__ __launch_bounds__(256) void k_bias(const double* __restrict__ M, int64_t ldm, int64_t l,
                                               int64_t l_pad, int64_t p,
                                               const double* __restrict__ q,
-                                              double* __restrict__ c64, float* __restrict__ c32) {
+                                              double* __restrict__ c64, float* __restrict__ c32,
+                                              double* __restrict__ rowmax) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= l_pad) return;
   double v = 0.0;
   if (i < l) {
-    double nn = 0.0;
-    for (int64_t k = 0; k < p; ++k) nn = fma(M[i * ldm + k], M[i * ldm + k], nn);
+    double nn = 0.0, mx = 0.0;
+    for (int64_t k = 0; k < p; ++k) {
+      const double x = M[i * ldm + k];
+      nn = fma(x, x, nn);
+      mx = fmax(mx, fabs(x));
+    }
     v = q[i] - nn;
+    rowmax[i] = mx;
   }
   c64[i] = v;
   c32[i] = (float)v;
+}
+
+// FP16 split scale: 2^s with the largest landmark magnitude at 2^12, so data
+// up to 16x larger than every landmark stays below the FP16 maximum.
+__global__ __launch_bounds__(256) void k_scale(const double* __restrict__ rowmax, int64_t l,
+                                               float* __restrict__ scales) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < l; i += 256) m = fmax(m, rowmax[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s2]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int e2 = 0;
+    if (sh[0] > 0.0) (void)frexp(sh[0], &e2);
+    const int sexp = 12 - e2;
+    scales[0] = ldexpf(1.0f, sexp);
+    scales[1] = ldexpf(1.0f, -2 * sexp);
+  }
 }
 
 // Operand packs of the embed kernels (see embed.hip for the layout):
 // FP32: row i, chunk ch -> 32 floats; split modes: 32 hi then 32 lo.
 __global__ void k_pack32(const double* __restrict__ M, int64_t ldm, int64_t l_pad, int64_t p,
                          int nch, float* __restrict__ m32, uint16_t* __restrict__ mbf,
-                         uint16_t* __restrict__ mh, float prescale, int* __restrict__ lo_flags) {
+                         uint16_t* __restrict__ mh, const float* __restrict__ scales,
+                         int* __restrict__ lo_flags) {
+  const float prescale = scales[0];
   const int64_t total = l_pad * (int64_t)nch * 32;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -606,23 +664,6 @@ __global__ void k_pack32(const double* __restrict__ M, int64_t ldm, int64_t l_pa
   }
 }
 
-__global__ __launch_bounds__(256) void k_maxabs(const double* __restrict__ M, int64_t ldm,
-                                                int64_t l, int64_t p, double* __restrict__ out) {
-  __shared__ double sh[256];
-  double m = 0.0;
-  for (int64_t e = threadIdx.x; e < l * p; e += 256) {
-    const int64_t i = e / p, k = e - (e / p) * p;
-    m = fmax(m, fabs(M[i * ldm + k]));
-  }
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = sh[0];
-}
-
 struct DevBuf {
   void* p = nullptr;
   hipStream_t st = nullptr;
@@ -639,6 +680,42 @@ struct DevBuf {
     if (_e != hipSuccess) return hip_fail(_e, what);          \
   } while (0)
 
+namespace {
+
+constexpr size_t kTriLdsMax = 150 * 1024;
+
+// Ritz solve of the k x k tridiagonal matrix; its work arrays live in LDS
+// when they fit.
+hipError_t launch_tridiag(const double* alpha, const double* beta, const int* ctrl, int k_host,
+                          int r, double* theta, double* bound, double* S, int ldS, double* gwork,
+                          int* kout, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tridiag),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTriLdsMax);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int nr = std::min(r, k_host);
+  const size_t base = sizeof(double) * 2 * (size_t)k_host;
+  const size_t work = sizeof(double) * 4 * (size_t)k_host * nr;
+  const int in_lds = (base + work <= kTriLdsMax) ? 1 : 0;
+  k_tridiag<<<1, 256, base + (in_lds ? work : 0), st>>>(alpha, beta, ctrl, k_host, r, theta, bound, S,
+                                                       ldS, gwork, kout, in_lds);
+  return hipGetLastError();
+}
+
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
+
+}  // namespace
+
 mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int64_t* idx_dev,
                          hipStream_t st) {
   const int64_t l = m.l, p = m.p, l_pad = m.l_pad;
@@ -649,65 +726,67 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   const int ldw = 16 * m.rb;
   const int kcap = (int)l;  // Krylov space can grow to the full dimension
 
-  // ---- model buffers (kept) ----
-  MDS_HIP(hipMalloc(&m.m64, sizeof(double) * l_pad * ldm));
-  MDS_HIP(hipMalloc(&m.m32, sizeof(float) * l_pad * nch32 * 32));
-  MDS_HIP(hipMalloc(&m.mbf, sizeof(uint16_t) * l_pad * nch32 * 64));
-  MDS_HIP(hipMalloc(&m.mh, sizeof(uint16_t) * l_pad * nch32 * 64));
-  MDS_HIP(hipMalloc(&m.w32, sizeof(float) * l_pad * ldw));
-  MDS_HIP(hipMalloc(&m.w64, sizeof(double) * l_pad * ldw));
-  MDS_HIP(hipMalloc(&m.c32, sizeof(float) * l_pad));
-  MDS_HIP(hipMalloc(&m.c64, sizeof(double) * l_pad));
-  m.bytes = (int64_t)(sizeof(double) * l_pad * ldm + sizeof(float) * l_pad * nch32 * 32 +
-                      2 * sizeof(uint16_t) * l_pad * nch32 * 64 +
-                      (sizeof(float) + sizeof(double)) * l_pad * (ldw + 1));
-  MDS_HIP(hipMemsetAsync(m.m64, 0, sizeof(double) * l_pad * ldm, st));
-  MDS_HIP(hipMemsetAsync(m.w32, 0, sizeof(float) * l_pad * ldw, st));
-  MDS_HIP(hipMemsetAsync(m.w64, 0, sizeof(double) * l_pad * ldw, st));
+  // ---- model buffers: one allocation ----
+  Layout lay;
+  const size_t o64 = lay.take(sizeof(double) * l_pad * ldm);
+  const size_t o32 = lay.take(sizeof(float) * l_pad * nch32 * 32);
+  const size_t obf = lay.take(sizeof(uint16_t) * l_pad * nch32 * 64);
+  const size_t oh = lay.take(sizeof(uint16_t) * l_pad * nch32 * 64);
+  const size_t ow32 = lay.take(sizeof(float) * l_pad * ldw);
+  const size_t ow64 = lay.take(sizeof(double) * l_pad * ldw);
+  const size_t oc32 = lay.take(sizeof(float) * l_pad);
+  const size_t oc64 = lay.take(sizeof(double) * l_pad);
+  MDS_HIP(hipMalloc(&m.base, lay.off));
+  char* b = static_cast<char*>(m.base);
+  m.m64 = b + o64;
+  m.m32 = b + o32;
+  m.mbf = b + obf;
+  m.mh = b + oh;
+  m.w32 = b + ow32;
+  m.w64 = b + ow64;
+  m.c32 = b + oc32;
+  m.c64 = b + oc64;
+  m.bytes = (int64_t)lay.off;
+  MDS_HIP(hipMemsetAsync(m.base, 0, lay.off, st));
 
-  // ---- scratch ----
-  DevBuf bDQ, bV, bsmall, bS, bwork, bVr, bX1;
-  const size_t nsmall = (size_t)l * 6 + 64;
+  // ---- scratch (stream-ordered, freed when the fit returns) ----
+  DevBuf bDQ, bV, bsmall, bS, bwork, bVr, bX1, bab;
   MDS_HIP(hipMallocAsync(&bDQ.p, sizeof(double) * l * l, st));
   bDQ.st = st;
   MDS_HIP(hipMallocAsync(&bV.p, sizeof(double) * l * (kcap + 1), st));
   bV.st = st;
-  MDS_HIP(hipMallocAsync(&bsmall.p, sizeof(double) * nsmall, st));
+  MDS_HIP(hipMallocAsync(&bsmall.p, sizeof(double) * ((size_t)l * 7 + 64), st));
   bsmall.st = st;
   MDS_HIP(hipMallocAsync(&bS.p, sizeof(double) * (size_t)(kcap + 1) * (r + 1), st));
   bS.st = st;
-  MDS_HIP(hipMallocAsync(&bwork.p, sizeof(double) * (size_t)(kcap + 1) * 5 * (r + 1), st));
+  MDS_HIP(hipMallocAsync(&bwork.p, sizeof(double) * (size_t)(kcap + 1) * 4 * (r + 1), st));
   bwork.st = st;
   MDS_HIP(hipMallocAsync(&bVr.p, sizeof(double) * l * r, st));
   bVr.st = st;
   MDS_HIP(hipMallocAsync(&bX1.p, sizeof(double) * l * r, st));
   bX1.st = st;
+  MDS_HIP(hipMallocAsync(&bab.p, sizeof(double) * ((size_t)2 * (kcap + 1) + 4 * MDS_MAX_R + 8), st));
+  bab.st = st;
   double* DQ = (double*)bDQ.p;
   double* Vk = (double*)bV.p;
-  double* sm = (double*)bsmall.p;
-  double* d1 = sm;
+  double* d1 = (double*)bsmall.p;
   double* q = d1 + l;
   double* rowsq = q + l;
   double* w = rowsq + l;
   double* h1 = w + l;
   double* h2 = h1 + l;
-  double* scal = h2 + l;        // [0] dbar, [1] |Q|_F, [2] maxabs
+  double* rowmax = h2 + l;
+  double* scal = rowmax + l;  // [0] dbar, [1] |Q|_F, [2..3] FP16 scales (as floats)
+  float* scales = reinterpret_cast<float*>(scal + 2);
   // ctrl: [0] stop, [1] stop step, [2] ok, [3] bad input, [4..5] lo flags,
   // [6] k of the last tridiagonal solve, [7] always 0 (no-stop view),
   // [8] k of the newest-run solve
-  int* ctrl = (int*)(scal + 8);
-  double* alpha = nullptr;
-  double* beta = nullptr;
-  double* theta = nullptr;
-  double* bound = nullptr;
-  DevBuf bab;
-  MDS_HIP(hipMallocAsync(&bab.p, sizeof(double) * ((size_t)2 * (kcap + 1) + 4 * MDS_MAX_R + 8), st));
-  bab.st = st;
-  alpha = (double*)bab.p;
-  beta = alpha + (kcap + 1);
-  theta = beta + (kcap + 1);
-  bound = theta + 2 * MDS_MAX_R;
-  MDS_HIP(hipMemsetAsync(ctrl, 0, sizeof(int) * 8, st));
+  int* ctrl = reinterpret_cast<int*>(scal + 8);
+  double* alpha = (double*)bab.p;
+  double* beta = alpha + (kcap + 1);
+  double* theta = beta + (kcap + 1);
+  double* bound = theta + 2 * MDS_MAX_R;
+  MDS_HIP(hipMemsetAsync(ctrl, 0, sizeof(int) * 16, st));
   MDS_HIP(hipMemsetAsync(beta, 0, sizeof(double) * (kcap + 1), st));
 
   // ---- gather, distances, centring ----
@@ -731,10 +810,9 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   k_mean<<<1, 256, 0, st>>>(d1, l, scal);
   k_centre<<<(unsigned)l, 256, 0, st>>>(DQ, l, d1, scal, q, rowsq);
   k_sqrt_sum<<<1, 256, 0, st>>>(rowsq, l, scal + 1);
-  k_maxabs<<<1, 256, 0, st>>>((const double*)m.m64, ldm, l, p, scal + 2);
   LAUNCH_CHECK("centring");
-  int hctrl[8];
-  double hscal[3];
+  int hctrl[16];
+  double hscal[2];
   MDS_HIP(hipMemcpyAsync(hctrl, ctrl, sizeof(hctrl), hipMemcpyDeviceToHost, st));
   MDS_HIP(hipMemcpyAsync(hscal, scal, sizeof(hscal), hipMemcpyDeviceToHost, st));
   MDS_HIP(hipStreamSynchronize(st));
@@ -743,9 +821,9 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   if (!(qnorm > 0.0)) return set_error(MDS_ERR_DEGENERATE, "all landmarks coincide (Q1 = 0)");
 
   // ---- Lanczos with full reorthogonalisation ----
-  const int rowblocks = (int)((l + 3) / 4);
-  const int upd_blocks = (int)((l + 255) / 256);
-  k_fill_random<<<upd_blocks, 256, 0, st>>>(w, l, 0x5EEDull);
+  const int upd_blocks = (int)((l + 63) / 64);
+  const int fill_blocks = (int)((l + 255) / 256);
+  k_fill_random<<<fill_blocks, 256, 0, st>>>(w, l, 0x5EEDull);
   k_set_column<<<1, 1024, 0, st>>>(Vk, l, 0, w, 0.0, ctrl + 2);
   LAUNCH_CHECK("lanczos start");
   const double conv_tol = 1e-13;
@@ -755,11 +833,11 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   std::vector<double> htheta(r), hbound(r);
   int k_final = 0;
   for (;;) {
-    const int batch = std::max(8, j / 8);
+    const int batch = std::max(std::max(8, r + 2 - j), j / 8);
     const int jend = std::min(kcap, j + batch);
     for (; j < jend; ++j) {
       const size_t shm = sizeof(double) * (size_t)(j + 1);
-      k_symv<<<rowblocks, 256, 0, st>>>(DQ, l, Vk + (int64_t)j * l, w, ctrl);
+      k_symv<<<(unsigned)l, 256, 0, st>>>(DQ, l, Vk + (int64_t)j * l, w, ctrl);
       k_dots<<<j + 1, 256, 0, st>>>(Vk, l, w, h1, ctrl);
       k_update<<<upd_blocks, 256, shm, st>>>(Vk, l, j + 1, h1, w, ctrl);
       k_dots<<<j + 1, 256, 0, st>>>(Vk, l, w, h2, ctrl);
@@ -768,9 +846,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
                                    (j + 1 < kcap) ? 1 : 0);
     }
     LAUNCH_CHECK("lanczos steps");
-    k_tridiag<<<1, 256, 0, st>>>(alpha, beta, ctrl, j, r, theta, bound, (double*)bS.p, kcap + 1,
-                                 (double*)bwork.p, ctrl + 6);
-    LAUNCH_CHECK("tridiagonal solve");
+    MDS_HIP(launch_tridiag(alpha, beta, ctrl, j, r, theta, bound, (double*)bS.p, kcap + 1,
+                           (double*)bwork.p, ctrl + 6, st));
     MDS_HIP(hipMemcpyAsync(hctrl, ctrl, sizeof(hctrl), hipMemcpyDeviceToHost, st));
     MDS_HIP(hipMemcpyAsync(htheta.data(), theta, sizeof(double) * r, hipMemcpyDeviceToHost, st));
     MDS_HIP(hipMemcpyAsync(hbound.data(), bound, sizeof(double) * r, hipMemcpyDeviceToHost, st));
@@ -790,11 +867,9 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
       // before it; once its largest Ritz value mu has converged, mu is the
       // largest eigenvalue left there.  Stop only if mu does not exceed
       // theta_r; otherwise further copies may hide in the complement.
-      k_tridiag<<<1, 256, 0, st>>>(alpha + block_start, beta + block_start, ctrl + 7,
-                                   k - block_start, 1, theta + r, bound + r,
-                                   (double*)bS.p + (size_t)(kcap + 1) * r, kcap + 1,
-                                   (double*)bwork.p + (size_t)(kcap + 1) * 5 * r, ctrl + 8);
-      LAUNCH_CHECK("tridiagonal solve (newest run)");
+      MDS_HIP(launch_tridiag(alpha + block_start, beta + block_start, ctrl + 7, k - block_start, 1,
+                             theta + r, bound + r, (double*)bS.p + (size_t)(kcap + 1) * r, kcap + 1,
+                             (double*)bwork.p + (size_t)(kcap + 1) * 4 * r, ctrl + 8, st));
       double hmu[2];
       MDS_HIP(hipMemcpyAsync(&hmu[0], theta + r, sizeof(double), hipMemcpyDeviceToHost, st));
       MDS_HIP(hipMemcpyAsync(&hmu[1], bound + r, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -811,7 +886,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
       bool ok = false;
       for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
         MDS_HIP(hipMemsetAsync(ctrl, 0, sizeof(int) * 2, st));
-        k_fill_random<<<upd_blocks, 256, 0, st>>>(w, l, 0xABCDull + 131ull * (uint64_t)(k + attempt));
+        k_fill_random<<<fill_blocks, 256, 0, st>>>(w, l, 0xABCDull + 131ull * (uint64_t)(k + attempt));
         const size_t shm = sizeof(double) * (size_t)k;
         for (int pass = 0; pass < 2; ++pass) {
           k_dots<<<k, 256, 0, st>>>(Vk, l, w, h1, ctrl);
@@ -854,44 +929,35 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     r_eff += live[t];
   }
   m.r_eff = r_eff;
-  DevBuf blive;
-  MDS_HIP(hipMallocAsync(&blive.p, sizeof(int) * r, st));
-  blive.st = st;
-  MDS_HIP(hipMemcpyAsync(blive.p, live.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
-  k_finalize_cols<<<r, 256, 0, st>>>((double*)bVr.p, l, r, theta, (const int*)blive.p,
-                                     (double*)bX1.p, (double*)m.w64, ldw, (float*)m.w32);
+  int* live_dev = ctrl + 16;  // room for MDS_MAX_R ints after the control words
+  MDS_HIP(hipMemcpyAsync(live_dev, live.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
+  k_finalize_cols<<<r, 256, 0, st>>>((double*)bVr.p, l, r, theta, live_dev, (double*)bX1.p,
+                                     (double*)m.w64, ldw, (float*)m.w32);
   k_bias<<<(unsigned)((l_pad + 255) / 256), 256, 0, st>>>((const double*)m.m64, ldm, l, l_pad, p, q,
-                                                        (double*)m.c64, (float*)m.c32);
-  LAUNCH_CHECK("finalise");
-
-  // FP16 split: scale by a power of two so the largest landmark magnitude
-  // sits at 2^12, leaving 16x headroom below the FP16 maximum for data.
-  const double maxabs = hscal[2];
-  int e2 = 0;
-  if (maxabs > 0.0) {
-    (void)frexp(maxabs, &e2);  // maxabs in [2^(e2-1), 2^e2)
-  }
-  const int sexp = 12 - e2;
-  m.h_prescale = ldexpf(1.0f, sexp);
-  m.h_postscale = ldexpf(1.0f, -2 * sexp);
+                                                        (double*)m.c64, (float*)m.c32, rowmax);
+  k_scale<<<1, 256, 0, st>>>(rowmax, l, scales);
   {
     const int64_t total = l_pad * (int64_t)nch32 * 32;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     k_pack32<<<grid, 256, 0, st>>>((const double*)m.m64, ldm, l_pad, p, nch32, (float*)m.m32,
-                                   (uint16_t*)m.mbf, (uint16_t*)m.mh, m.h_prescale, ctrl + 4);
-    LAUNCH_CHECK("pack");
+                                   (uint16_t*)m.mbf, (uint16_t*)m.mh, scales, ctrl + 4);
+    LAUNCH_CHECK("finalise");
   }
   // ---- host copies ----
   m.lam_host = new double[r];
   m.x1_host = new double[(size_t)l * r];
   m.q_host = new double[(size_t)l];
   for (int t = 0; t < r; ++t) m.lam_host[t] = htheta[t];
+  float hsc[2];
   MDS_HIP(hipMemcpyAsync(m.x1_host, bX1.p, sizeof(double) * l * r, hipMemcpyDeviceToHost, st));
   MDS_HIP(hipMemcpyAsync(m.q_host, q, sizeof(double) * l, hipMemcpyDeviceToHost, st));
   MDS_HIP(hipMemcpyAsync(hctrl, ctrl, sizeof(hctrl), hipMemcpyDeviceToHost, st));
+  MDS_HIP(hipMemcpyAsync(hsc, scales, sizeof(hsc), hipMemcpyDeviceToHost, st));
   MDS_HIP(hipStreamSynchronize(st));
   m.bf_lo_zero = hctrl[4] ? 0 : 1;
   m.h_lo_zero = hctrl[5] ? 0 : 1;
+  m.h_prescale = hsc[0];
+  m.h_postscale = hsc[1];
   return MDS_OK;
 }
 

@@ -63,7 +63,8 @@ struct Model {
   double* lam_host = nullptr;   // r
   double* x1_host = nullptr;    // l x r
   double* q_host = nullptr;     // l
-  // device buffers
+  // device buffers: one allocation (base), the rest point into it
+  void* base = nullptr;
   void* m64 = nullptr;    // l_pad x nchunks64 x 16 doubles (FP64 operand and fit input)
   void* m32 = nullptr;    // l_pad x nchunks32 x 32 floats
   void* mbf = nullptr;    // l_pad x nchunks32 x (32 hi + 32 lo) bf16
