@@ -13,6 +13,7 @@ the host cores (bounded sample).
 
     python bench.py [--steps K] [--warmup W] [--workload wide|image]
     python bench.py --only-embed fp32 --iters 20     (for rocprofv3 runs)
+    python bench.py --only-fit --iters 5              (for rocprofv3 runs)
     python bench.py --copy-calib 1073741824           (counter calibration)
 """
 
@@ -191,6 +192,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--only-embed", choices=["fp32", "split_bf16", "split_fp16", "fp64"])
     ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--only-fit", action="store_true", help="run --iters fits only (profiling)")
     ap.add_argument("--copy-calib", type=int, default=0)
     args = ap.parse_args()
 
@@ -220,6 +222,13 @@ def main():
     X = make_data(args.workload)
     Xd = torch.from_numpy(X).to(dev)
     torch.cuda.synchronize()
+
+    if args.only_fit:
+        for _ in range(args.iters):
+            mds.fit_landmarks(Xd, w["l"], w["r"], seed=0).free()
+        torch.cuda.synchronize()
+        print(json.dumps({"only_fit": args.iters}))
+        return
 
     if args.only_embed:
         model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)

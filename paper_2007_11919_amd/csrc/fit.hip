@@ -588,27 +588,33 @@ __global__ __launch_bounds__(256) void k_finalize_cols(double* __restrict__ Vr, 
 }
 
 // c = q - |m|^2 per landmark (zero for padding rows), FP64 and FP32; also
-// the largest |m| of each landmark row
+// the largest |m| of each landmark row.  One wave per row, fixed order.
 __global__ __launch_bounds__(256) void k_bias(const double* __restrict__ M, int64_t ldm, int64_t l,
                                               int64_t l_pad, int64_t p,
                                               const double* __restrict__ q,
                                               double* __restrict__ c64, float* __restrict__ c32,
                                               double* __restrict__ rowmax) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= l_pad) return;
-  double v = 0.0;
-  if (i < l) {
-    double nn = 0.0, mx = 0.0;
-    for (int64_t k = 0; k < p; ++k) {
+  double nn = 0.0, mx = 0.0;
+  if (i < l)
+    for (int64_t k = lane; k < p; k += 64) {
       const double x = M[i * ldm + k];
       nn = fma(x, x, nn);
       mx = fmax(mx, fabs(x));
     }
-    v = q[i] - nn;
-    rowmax[i] = mx;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    nn += __shfl_xor(nn, off, 64);
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
   }
-  c64[i] = v;
-  c32[i] = (float)v;
+  if (lane == 0) {
+    const double v = (i < l) ? q[i] - nn : 0.0;
+    if (i < l) rowmax[i] = mx;
+    c64[i] = v;
+    c32[i] = (float)v;
+  }
 }
 
 // FP16 split scale: 2^s with the largest landmark magnitude at 2^12, so data
@@ -832,8 +838,12 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   int restarts = 0;
   std::vector<double> htheta(r), hbound(r);
   int k_final = 0;
+  // Steps until the next convergence check: grown from the observed decay
+  // rate of the slowest residual bound (a check costs a host round trip).
+  int batch = std::max(8, r + 2);
+  int prev_j = -1;
+  double prev_worst = 0.0;
   for (;;) {
-    const int batch = std::max(std::max(8, r + 2 - j), j / 8);
     const int jend = std::min(kcap, j + batch);
     for (; j < jend; ++j) {
       const size_t shm = sizeof(double) * (size_t)(j + 1);
@@ -881,6 +891,21 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
       k_final = k;
       break;
     }
+    {
+      double worst = 0.0;
+      for (int t = 0; t < std::min(r, k); ++t) worst = std::max(worst, hbound[t] / fabs(htheta[0]));
+      int next = 8;
+      if (prev_j >= 0 && worst > 0.0 && prev_worst > worst && j > prev_j) {
+        const double rate = (log(prev_worst) - log(worst)) / (double)(j - prev_j);  // per step
+        const double need = (log(worst) - log(conv_tol)) / rate;
+        next = (int)std::ceil(need * 1.05) + 1;
+      } else if (prev_j >= 0) {
+        next = std::max(8, j / 4);
+      }
+      batch = std::min(std::max(next, 4), std::max(8, j));
+      prev_j = j;
+      prev_worst = worst;
+    }
     if (stopped) {
       // Invariant subspace: continue with a fresh vector orthogonal to it.
       bool ok = false;
@@ -906,6 +931,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
       }
       j = k;
       block_start = k;
+      prev_j = -1;  // a new run: its residuals start over
+      batch = 8;
     } else if (j >= kcap) {
       k_final = k;
       break;
@@ -933,7 +960,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   MDS_HIP(hipMemcpyAsync(live_dev, live.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
   k_finalize_cols<<<r, 256, 0, st>>>((double*)bVr.p, l, r, theta, live_dev, (double*)bX1.p,
                                      (double*)m.w64, ldw, (float*)m.w32);
-  k_bias<<<(unsigned)((l_pad + 255) / 256), 256, 0, st>>>((const double*)m.m64, ldm, l, l_pad, p, q,
+  k_bias<<<(unsigned)((l_pad + 3) / 4), 256, 0, st>>>((const double*)m.m64, ldm, l, l_pad, p, q,
                                                         (double*)m.c64, (float*)m.c32, rowmax);
   k_scale<<<1, 256, 0, st>>>(rowmax, l, scales);
   {
