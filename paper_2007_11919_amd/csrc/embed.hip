@@ -165,18 +165,40 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
   const T* cvec = reinterpret_cast<const T*>(mv.c);
   const T* wmat = reinterpret_cast<const T*>(mv.w);
 
+  // Fast path: rows 16-byte aligned and p a multiple of the segment width, so
+  // every segment is wholly inside or wholly outside the data; the loads
+  // then issue without branches (clamped address, zero selected outside).
+  const bool xfast = xvec && (p % E == 0) && (sizeof(TX) * E == 16);
   auto load_chunk = [&](int lt, int ch) {
     const int64_t k0 = (int64_t)ch * Tt::CH + lseg * E;
+    if (xfast) {
+      const bool kin = k0 < p;
+      const int64_t kk = kin ? k0 : 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = lrow + 32 * u;
+        const bool in = kin && (row < nrows);
+        const int64_t rr = (row < nrows) ? row : 0;
+        const u4 raw = *reinterpret_cast<const u4*>(X + rr * ldx + kk);
+        const u4 z = {0u, 0u, 0u, 0u};
+        const u4 v = in ? raw : z;
+        __builtin_memcpy(&xr[u], &v, 16);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = lrow + 32 * u;
+        if (row < nrows) {
+          xr[u] = load_seg<TX, E>(X + (int64_t)row * ldx, k0, p, xvec);
+        } else {
+#pragma unroll
+          for (int i = 0; i < E; ++i) xr[u].v[i] = (TX)0;
+        }
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int row = lrow + 32 * u;
-      if (row < nrows) {
-        xr[u] = load_seg<TX, E>(X + (int64_t)row * ldx, k0, p, xvec);
-      } else {
-#pragma unroll
-        for (int i = 0; i < E; ++i) xr[u].v[i] = (TX)0;
-      }
-      const int64_t lm = (int64_t)lt * BN + row;
+      const int64_t lm = (int64_t)lt * BN + lrow + 32 * u;
       mr[u] = *reinterpret_cast<const u4*>(mbase + (lm * nch + ch) * CHUNK_BYTES + lseg * 16);
     }
   };
