@@ -314,8 +314,15 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       T cv[4];
+      if constexpr (MODE == MODE_F64) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) cv[v] = cvec[lbase + 16 * i + acc_row<MODE>(lg, v)];
+        for (int v = 0; v < 4; ++v) cv[v] = cvec[lbase + 16 * i + acc_row<MODE>(lg, v)];
+      } else {
+        // the lane's four landmarks are consecutive: one vector load
+        const f4 c4 = *reinterpret_cast<const f4*>(cvec + lbase + 16 * i + 4 * lg);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cv[v] = c4[v];
+      }
       Acc e[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -325,9 +332,17 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
       for (int rb = 0; rb < RB; ++rb) {
         if (rb < rb_rt) {
           T wv[4];
+          if constexpr (MODE == MODE_F64) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            wv[v] = wmat[(lbase + 16 * i + acc_row<MODE>(lg, v)) * ldw + 16 * rb + lr];
+            for (int v = 0; v < 4; ++v)
+              wv[v] = wmat[(lbase + 16 * i + acc_row<MODE>(lg, v)) * ldw + 16 * rb + lr];
+          } else {
+            // FP32 weights are stored column-major (output column, landmark)
+            const f4 w4 = *reinterpret_cast<const f4*>(wmat + (int64_t)(16 * rb + lr) * mv.ldwt +
+                                                       lbase + 16 * i + 4 * lg);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) wv[v] = w4[v];
+          }
 #pragma unroll
           for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -346,17 +361,13 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
     const int nz = store_chunk(0);
     xlo_cur = __syncthreads_or(nz);
   }
+  int lt = 0, ch = 0;
   for (int it = 0; it < total; ++it) {
     const int buf = it & 1;
-    const int lt = it / nch;
-    const int ch = it - lt * nch;
     const bool has_next = it + 1 < total;
-    int nlt = 0, nchn = 0;
-    if (has_next) {
-      nlt = (it + 1) / nch;
-      nchn = (it + 1) - nlt * nch;
-      load_chunk(nlt, nchn);
-    }
+    const int nchn = (ch + 1 == nch) ? 0 : ch + 1;
+    const int nlt = (ch + 1 == nch) ? lt + 1 : lt;
+    if (has_next) load_chunk(nlt, nchn);
     compute_chunk(buf, ch, xlo_cur != 0);
     int nz = 0;
     if (has_next) {
@@ -383,6 +394,8 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
       }
       epilogue(lt);
     }
+    lt = nlt;
+    ch = nchn;
   }
 
   // ---- combine the two landmark halves (fixed order) and store ----
@@ -521,12 +534,14 @@ EmbedModelView Model::view(int mode) const {
     case MODE_F32:
       v.mpack = m32;
       v.w = w32;
+      v.ldwt = l_pad;
       v.c = c32;
       v.nchunks = (int)((p + 31) / 32);
       break;
     case MODE_BF16:
       v.mpack = mbf;
       v.w = w32;
+      v.ldwt = l_pad;
       v.c = c32;
       v.nchunks = (int)((p + 31) / 32);
       v.m_lo_zero = bf_lo_zero;
@@ -534,6 +549,7 @@ EmbedModelView Model::view(int mode) const {
     default:
       v.mpack = mh;
       v.w = w32;
+      v.ldwt = l_pad;
       v.c = c32;
       v.nchunks = (int)((p + 31) / 32);
       v.m_lo_zero = h_lo_zero;

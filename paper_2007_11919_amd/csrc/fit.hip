@@ -544,7 +544,7 @@ __global__ __launch_bounds__(256) void k_finalize_cols(double* __restrict__ Vr, 
                                                        const int* __restrict__ live,
                                                        double* __restrict__ X1,
                                                        double* __restrict__ W64, int ldw,
-                                                       float* __restrict__ W32) {
+                                                       float* __restrict__ W32t, int64_t l_pad) {
   __shared__ double shv[256];
   __shared__ int64_t shi[256];
   const int tt = blockIdx.x;
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(256) void k_finalize_cols(double* __restrict__ Vr, 
     X1[i * r + tt] = on ? v * sx : 0.0;
     const double wv = on ? v * sw : 0.0;
     W64[i * ldw + tt] = wv;
-    W32[i * ldw + tt] = (float)wv;
+    W32t[(int64_t)tt * l_pad + i] = (float)wv;
   }
 }
 
@@ -959,7 +959,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   int* live_dev = ctrl + 16;  // room for MDS_MAX_R ints after the control words
   MDS_HIP(hipMemcpyAsync(live_dev, live.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
   k_finalize_cols<<<r, 256, 0, st>>>((double*)bVr.p, l, r, theta, live_dev, (double*)bX1.p,
-                                     (double*)m.w64, ldw, (float*)m.w32);
+                                     (double*)m.w64, ldw, (float*)m.w32, l_pad);
   k_bias<<<(unsigned)((l_pad + 3) / 4), 256, 0, st>>>((const double*)m.m64, ldm, l, l_pad, p, q,
                                                         (double*)m.c64, (float*)m.c32, rowmax);
   k_scale<<<1, 256, 0, st>>>(rowmax, l, scales);

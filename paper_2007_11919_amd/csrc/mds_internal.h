@@ -30,7 +30,8 @@ inline int chunk_elems(int mode) { return mode == MODE_F64 ? 16 : 32; }
 // Device-side view of one model for one precision, passed by value.
 struct EmbedModelView {
   const void* mpack;   // l_pad rows x nchunks x CHUNK_BYTES landmark operands
-  const void* w;       // l_pad x (16*rb) projection weights (float or double)
+  const void* w;       // projection weights: FP64 l_pad x (16*rb) row-major;
+                       // FP32 (16*rb) x l_pad (column-major, leading dim ldwt)
   const void* c;       // l_pad: q - |m|^2 (float or double)
   int p;               // data dimension
   int nchunks;         // ceil(p / chunk_elems)
@@ -40,6 +41,7 @@ struct EmbedModelView {
   int m_lo_zero;       // split modes: every landmark lo part is zero
   float prescale;      // split FP16: data scaled by 2^s before splitting
   float postscale;     // split FP16: 2^-2s applied to the dot products
+  int64_t ldwt;        // leading dimension of the FP32 weights
 };
 
 // One row tile of one request, for the persistent serving kernel.
@@ -69,7 +71,7 @@ struct Model {
   void* m32 = nullptr;    // l_pad x nchunks32 x 32 floats
   void* mbf = nullptr;    // l_pad x nchunks32 x (32 hi + 32 lo) bf16
   void* mh = nullptr;     // same for FP16 (scaled)
-  void* w32 = nullptr;    // l_pad x 16rb float
+  void* w32 = nullptr;    // 16rb x l_pad float (column-major: output column, landmark)
   void* w64 = nullptr;    // l_pad x 16rb double
   void* c32 = nullptr;    // l_pad float
   void* c64 = nullptr;    // l_pad double
