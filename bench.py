@@ -150,6 +150,90 @@ def serving_run(mds, torch, model, Xd, prec, count, seed, budget):
     return out
 
 
+def serving_multi(mds, torch, count, seed, budget, precs=("fp32", "split_bf16")):
+    """Multi-tenant serving: 48 fitted models (p in {10, 50, 100, 784} x r in
+    {2, 5, 10, 20} x 3, l log-uniform in [500, 4000]) resident under a byte
+    budget; a stream of requests (sizes log-uniform in [1, 500,000], model
+    uniform) at 0.8 of the measured saturated rate.  A sample of results is
+    compared bit for bit with a plain mds_embed of the same rows."""
+    from paper_2007_11919_amd.serve import Server
+    from synth import generators as gen
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pool_rows = 500_000
+    pools = {
+        10: gen.gaussian_columns(pool_rows, gen.SIGMAS_SMALL, 21, dtype=np.float32),
+        50: gen.gaussian_columns(pool_rows, gen.SIGMAS_P50, 22, dtype=np.float32),
+        100: gen.wide_gaussian(pool_rows, seed=23),
+        784: gen.image_mixture(pool_rows, seed=24),
+    }
+    dpools = {p: torch.from_numpy(x).cuda() for p, x in pools.items()}
+    del pools
+    models = []
+    t = time.perf_counter()
+    for rep in range(3):
+        for p in (10, 50, 100, 784):
+            for r in (2, 5, 10, 20):
+                l = int(round(np.exp(rng.uniform(np.log(500), np.log(4000)))))
+                models.append((p, mds.fit_landmarks(dpools[p], l, r, seed=rep * 100 + p + r)))
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t
+    out = {"models": len(models), "budget_bytes": budget, "fit_all_s": fit_s,
+           "model_bytes": int(sum(m.nbytes for _, m in models)), "runs": []}
+    sizes = gen.request_sizes(count, 500_000, seed + 1)
+    which = rng.integers(0, len(models), size=count)
+    offs = [int(rng.integers(0, pool_rows - s + 1)) for s in sizes]
+    for prec in precs:
+        srv = Server(budget_bytes=budget, max_slots=512, tiles_per_step=4096)
+        ids = [srv.add_model(m) for _, m in models]
+        ys = [None] * count
+
+        def run(arrivals):
+            tickets = []
+            t0 = srv.now() + 0.002
+            for i in range(count):
+                if arrivals is not None:
+                    while srv.now() < t0 + arrivals[i]:
+                        pass
+                p, m = models[which[i]]
+                s, o = int(sizes[i]), offs[i]
+                if ys[i] is None:
+                    ys[i] = torch.empty((s, m.r), dtype=torch.float32, device="cuda")
+                tickets.append(srv.submit(ids[which[i]], dpools[p][o:o + s], prec, ys[i]))
+            for tk in tickets:
+                srv.wait(tk, timeout=1200.0)
+            recs = [srv.poll(tk) for tk in tickets]
+            done = np.array([r["t_done"] for r in recs])
+            if arrivals is None:
+                return done.max() - min(r["t_submit"] for r in recs), None
+            return done.max() - t0, done - (t0 + arrivals)
+
+        makespan, _ = run(None)
+        cap = count / makespan
+        arr = gen.poisson_arrivals(count, 0.8 * cap, seed + 2)
+        span, lat = run(arr)
+        # bit-for-bit check of a sample against plain mds_embed
+        same = True
+        for i in range(0, count, max(1, count // 50)):
+            p, m = models[which[i]]
+            s, o = int(sizes[i]), offs[i]
+            ref = mds.embed(m, dpools[p][o:o + s], prec=prec)
+            same &= bool(torch.equal(ref, ys[i]))
+        st = srv.stats()
+        srv.close()
+        out["runs"].append({
+            "precision": prec, "requests": count, "points": int(sizes.sum()),
+            "saturated_points_per_s": float(sizes.sum() / makespan),
+            "rate_requests_per_s": float(0.8 * cap),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "points_per_s_at_load": float(sizes.sum() / span),
+            "steps": int(st["steps"]), "bitwise_equal_to_plain_embed": same})
+        del ys
+    for _, m in models:
+        m.free()
+    return out
+
+
 def cpu_baseline(name, X, w, sample_rows, Ys_gpu):
     """The FP64 oracle, as it stands, on the host cores: full fit plus the
     embed of a bounded sample of rows, scaled to rows per second of a whole
@@ -188,6 +272,8 @@ def main():
     ap.add_argument("--embed-iters", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-multi", type=int, default=0,
+                    help="also run the 48-model multi-tenant serving mix with this many requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--only-embed", choices=["fp32", "split_bf16", "split_fp16", "fp64"])
@@ -310,6 +396,9 @@ def main():
         out["serving"] = {"budget_bytes": budget, "runs": [
             serving_run(mds, torch, model, Xd, prec, args.serve_requests, 5, budget)
             for prec in ("fp32", "split_bf16")]}
+    if args.serve_multi:
+        log("multi-tenant serving")
+        out["serving_multi"] = serving_multi(mds, torch, args.serve_multi, 31, 24 << 30)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         base, errs = cpu_baseline(args.workload, X, w, args.cpu_sample,

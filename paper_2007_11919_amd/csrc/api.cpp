@@ -5,8 +5,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "mds_internal.h"
@@ -33,10 +35,51 @@ mds_status hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? MDS_ERR_OOM : MDS_ERR_HIP;
 }
 
+// Freed model blocks are kept for reuse by later fits of the same size, so
+// a steady stream of fit/free pairs does not pay hipMalloc / hipFree (which
+// synchronises the device) every time.  Bounded by count and bytes.
+namespace {
+constexpr size_t kCacheBlocks = 8;
+constexpr size_t kCacheBytes = (size_t)1 << 30;
+std::mutex g_cache_mu;
+std::vector<std::tuple<int, size_t, void*>> g_cache;  // (device, bytes, pointer)
+size_t g_cache_total = 0;
+}  // namespace
+
+void* model_alloc(int dev, size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+      if (std::get<0>(g_cache[i]) == dev && std::get<1>(g_cache[i]) == bytes) {
+        void* p = std::get<2>(g_cache[i]);
+        g_cache_total -= bytes;
+        g_cache.erase(g_cache.begin() + (ptrdiff_t)i);
+        return p;
+      }
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void model_release(int dev, size_t bytes, void* p) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_cache.size() < kCacheBlocks && g_cache_total + bytes <= kCacheBytes) {
+      g_cache.emplace_back(dev, bytes, p);
+      g_cache_total += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
 namespace {
 
 void free_model(Model& m) {
-  if (m.base) (void)hipFree(m.base);
+  if (m.base) model_release(m.dev, (size_t)m.bytes, m.base);
   delete[] m.idx_host;
   delete[] m.lam_host;
   delete[] m.x1_host;

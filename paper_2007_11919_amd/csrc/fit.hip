@@ -742,7 +742,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   const size_t ow64 = lay.take(sizeof(double) * l_pad * ldw);
   const size_t oc32 = lay.take(sizeof(float) * l_pad);
   const size_t oc64 = lay.take(sizeof(double) * l_pad);
-  MDS_HIP(hipMalloc(&m.base, lay.off));
+  m.base = model_alloc(m.dev, lay.off);
+  if (!m.base) return set_error(MDS_ERR_OOM, "device allocation of the model failed");
   char* b = static_cast<char*>(m.base);
   m.m64 = b + o64;
   m.m32 = b + o32;

@@ -91,6 +91,10 @@ mds_status hip_fail(hipError_t e, const char* what);
     if (_e != hipSuccess) return ::mds::hip_fail(_e, #call);           \
   } while (0)
 
+// ---- model memory (api.cpp): a small cache of freed model blocks --------
+void* model_alloc(int dev, size_t bytes);
+void model_release(int dev, size_t bytes, void* p);
+
 // ---- host sampler (sampler.cpp) -----------------------------------------
 void sample_landmarks_host(int64_t n, int64_t l, uint64_t seed, int64_t* out);
 
