@@ -234,6 +234,41 @@ def serving_multi(mds, torch, count, seed, budget, precs=("fp32", "split_bf16"))
     return out
 
 
+def sqdist_leg(mds, torch, model, Xd, Y32, iters):
+    """mds_embed_from_sqdist on the n x l block of squared distances from
+    every row to the landmarks (FP32, built on the device beforehand as
+    input).  Memory-bound: reported against the HBM peak."""
+    idx = torch.from_numpy(model.landmarks()).to(Xd.device)
+    M = Xd[idx]
+    n, l = Xd.shape[0], M.shape[0]
+    A2 = torch.empty((n, l), dtype=torch.float32, device=Xd.device)
+    mn = (M * M).sum(1)
+    for s in range(0, n, 100_000):
+        xb = Xd[s:s + 100_000]
+        A2[s:s + 100_000] = ((xb * xb).sum(1, keepdim=True) + mn[None, :] - 2.0 * (xb @ M.T)).clamp_min_(0)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    Y = mds.embed_from_sqdist(model, A2, prec="fp32")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(iters):
+        mds.embed_from_sqdist(model, A2, prec="fp32", Y=Y)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / iters
+    nbytes = 4.0 * n * l + 4.0 * n * model.r
+    from synth import errors
+    err = errors.column_errors(Y.cpu().numpy(), Y32.cpu().numpy())
+    del A2
+    return {"ms": t * 1e3, "points_per_s": n / t,
+            "roofline": {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM / 1e9,
+                         "unit": "GB/s", "frac": nbytes / t / PEAK_HBM,
+                         "bytes_per_launch": nbytes},
+            "rms_rel_vs_fp32_embed": err["rms_rel"]}
+
+
 def cpu_baseline(name, X, w, sample_rows, Ys_gpu):
     """The FP64 oracle, as it stands, on the host cores: full fit plus the
     embed of a bounded sample of rows, scaled to rows per second of a whole
@@ -272,6 +307,7 @@ def main():
     ap.add_argument("--embed-iters", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-sqdist", action="store_true")
     ap.add_argument("--serve-multi", type=int, default=0,
                     help="also run the 48-model multi-tenant serving mix with this many requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -390,6 +426,9 @@ def main():
         "paper_context": "paper: 18.34 s for n=1e6, 100 columns, l=250, r=10 on one i9-10900K "
                          "in R (about 54,500 points/s); different l, not a target",
     }
+    if args.workload == "wide" and not args.no_sqdist:
+        log("embedding from squared dissimilarities")
+        out["embed_from_sqdist"] = sqdist_leg(mds, torch, model, Xd, Y32, args.embed_iters)
     if not args.no_serve:
         log("serving runs")
         budget = 8 << 30

@@ -118,6 +118,32 @@ mds_status mds_fit_landmarks(const void* X, int32_t dt, int64_t n, int64_t p,
 mds_status mds_embed(const mds_model* m, const void* X, int32_t dt, int64_t n_new,
                      int64_t ldx, int32_t prec, void* Y, int64_t ldy, void* stream);
 
+/* ---- dissimilarity input (Section 2 starts from a matrix of squared
+ * dissimilarities; they need not be squared Euclidean distances) ----------
+ * D1:  device, l x l FP64, row-major with ldd >= l: squared dissimilarities
+ *      among the l landmark points.  Symmetric (|d_ij - d_ji| <= 1e-12
+ *      (|d_ij| + |d_ji|)) and finite, else INVALID_ARG; it is symmetrised
+ *      exactly before use.  Negative eigenvalues of Q1 are allowed: only the
+ *      r largest are kept and non-positive ones are dead directions.
+ * The fit runs from the double centring on, exactly as in
+ * mds_fit_landmarks.  The model holds no landmark vectors: mds_embed on it
+ * returns INVALID_ARG; use mds_embed_from_sqdist.  It reports n_fit = l
+ * and p = 0, and its landmarks are 0..l-1.  Synchronous; errors as mds_fit_landmarks. */
+mds_status mds_fit_from_sqdist(const double* D1, int64_t l, int64_t ldd, int32_t r, void* stream,
+                               mds_model** out);
+
+/* Eq. (2) for n_new points given their squared dissimilarities to the l
+ * landmarks:  y = 1/2 Lambda^{-1/2} V' (q1 - a).
+ * A2:  device, n_new x l, leading dimension lda >= l, element type dt.
+ * prec MDS_PREC_FP64 (Y double; A2 F32 or F64) or MDS_PREC_FP32 (Y float;
+ *      A2 F32).  Works with models from either fit (for a model fitted on
+ *      vectors, a = squared distances to the landmarks gives mds_embed's
+ *      result).  Asynchronous on `stream`; a memory-bound streaming kernel.
+ * Errors: INVALID_ARG (null pointers, lda < l, ldy < r, dt/prec mismatch),
+ * HIP. */
+mds_status mds_embed_from_sqdist(const mds_model* m, const void* A2, int32_t dt, int64_t n_new,
+                                 int64_t lda, int32_t prec, void* Y, int64_t ldy, void* stream);
+
 /* Release every device and host buffer of the model.  NULL is a no-op.
  * The caller must ensure no embed on any stream still uses m. */
 void mds_free(mds_model* m);

@@ -13,18 +13,23 @@ Pin status (what fixes each part independently of this code):
 * interpolation - landmark self-reproduction, Proposition 1 (eq. (3)),
                   exact recovery of data lying in R^r, l = n reduces to
                   classical MDS, invariance under rigid motions.
+* dissimilarity input (fit_from_sqdist, interpolate_sqdist) - equals the
+                  vector path on Euclidean input; brute-force Jacobi on a
+                  non-Euclidean matrix; self-reproduction and Proposition 1
+                  for non-Euclidean input.
 No function is left "parity unpinned".
 """
 
-from .mds import (TAU, DegenerateError, Fit, classical_mds, fit_landmarks,
-                  gower_block, inner_products, interpolate, interpolation_mds,
+from .mds import (TAU, DegenerateError, Fit, classical_mds, fit_from_sqdist, fit_landmarks,
+                  gower_block, inner_products, interpolate, interpolate_sqdist, interpolation_mds,
                   interpolation_mds_paper_layout, lmds_block, sign_convention,
                   sqdist_rows, sqdist_rows_expanded, top_eigenpairs)
 from .sampler import SplitMix64, bounded, fisher_yates_prefix, sample_landmarks
 from .linalg_small import jacobi_eigh, procrustes
 
 __all__ = [
-    "TAU", "DegenerateError", "Fit", "classical_mds", "fit_landmarks",
+    "TAU", "DegenerateError", "Fit", "classical_mds", "fit_from_sqdist", "fit_landmarks",
+    "interpolate_sqdist",
     "gower_block", "inner_products", "interpolate", "interpolation_mds",
     "interpolation_mds_paper_layout", "lmds_block", "sign_convention",
     "sqdist_rows", "sqdist_rows_expanded", "top_eigenpairs", "SplitMix64",

@@ -194,6 +194,25 @@ def interpolate(fit, Xnew, block=None, formula=gower_block, expanded=None):
     return Y
 
 
+def fit_from_sqdist(D1, r):
+    """Classical MDS of l points given only their l x l squared
+    dissimilarities (Section 2 starts from such a matrix; it need not come
+    from Euclidean vectors, so Q1 may have negative eigenvalues)."""
+    D1 = np.asarray(D1, dtype=np.float64)
+    l = D1.shape[0]
+    X1, lam, V, live, Q1 = classical_mds(D1, r)
+    return Fit(idx=np.arange(l, dtype=np.int64), M=np.zeros((l, 0)), D1=D1, Q1=Q1,
+               q=np.diag(Q1).copy(), d1=D1.mean(axis=1), dbar=float(D1.mean()), lam=lam, V=V,
+               live=live, X1=X1, r_eff=int(live.sum()))
+
+
+def interpolate_sqdist(fit, A2, formula=None):
+    """Eq. (2) for new points given their squared dissimilarities A2 (m x l)
+    to the landmarks."""
+    formula = gower_block if formula is None else formula
+    return formula(fit, np.asarray(A2, dtype=np.float64))
+
+
 def interpolation_mds(X, l, r, seed=0, idx=None):
     """Interpolation MDS of the data X: fit on l landmarks, then interpolate
     all n rows (landmarks included) in input order."""

@@ -187,6 +187,39 @@ def embed(model, X, prec="fp32", Y=None, stream=None):
     return Y
 
 
+def fit_from_sqdist(D1, r, stream=None):
+    """mds_fit_from_sqdist: classical MDS of l points from their l x l
+    squared dissimilarities (device float64 tensor)."""
+    import torch
+    _check_matrix(D1, "D1")
+    if D1.dtype != torch.float64 or D1.shape[0] != D1.shape[1]:
+        raise ValueError("D1 must be a square float64 device tensor")
+    l = D1.shape[0]
+    out = ctypes.c_void_p()
+    _check(_lib.lib().mds_fit_from_sqdist(ctypes.c_void_p(D1.data_ptr()), l,
+                                          D1.stride(0) if l > 1 else 1, int(r),
+                                          _stream_ptr(stream), ctypes.byref(out)))
+    return Model(out.value)
+
+
+def embed_from_sqdist(model, A2, prec="fp32", Y=None, stream=None):
+    """mds_embed_from_sqdist: eq. (2) for rows of squared dissimilarities
+    A2 (n x l device tensor) to the model's landmarks."""
+    import torch
+    _check_matrix(A2, "A2")
+    n = A2.shape[0]
+    code = PREC[prec]
+    ydt = torch.float64 if code == PREC["fp64"] else torch.float32
+    if Y is None:
+        Y = torch.empty((n, model.r), dtype=ydt, device=A2.device)
+    lda = A2.stride(0) if n > 1 else A2.shape[1]
+    ldy = Y.stride(0) if n > 1 else Y.shape[1]
+    _check(_lib.lib().mds_embed_from_sqdist(model.handle, ctypes.c_void_p(A2.data_ptr()),
+                                            _dtype_code(A2), n, lda, code,
+                                            ctypes.c_void_p(Y.data_ptr()), ldy, _stream_ptr(stream)))
+    return Y
+
+
 def free(model):
     """mds_free."""
     model.free()

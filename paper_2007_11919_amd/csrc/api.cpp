@@ -171,7 +171,7 @@ mds_status mds_fit_landmarks(const void* X, int32_t dt, int64_t n, int64_t p, in
     return hip_fail(e, "hipMallocAsync(idx)");
   }
   e = hipMemcpyAsync(idx_dev, m.idx_host, sizeof(int64_t) * l, hipMemcpyHostToDevice, st);
-  mds_status s = (e == hipSuccess) ? fit_on_device(m, X, dt, ldx, idx_dev, st)
+  mds_status s = (e == hipSuccess) ? fit_on_device(m, X, dt, ldx, idx_dev, nullptr, 0, st)
                                    : hip_fail(e, "hipMemcpyAsync(idx)");
   (void)hipFreeAsync(idx_dev, st);
   if (s == MDS_OK) {
@@ -199,6 +199,9 @@ mds_status mds_embed(const mds_model* h, const void* X, int32_t dt, int64_t n_ne
   if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
   if (prec != MDS_PREC_FP64 && dt != MDS_F32)
     return set_error(MDS_ERR_INVALID_ARG, "FP32 and split precisions take MDS_F32 input");
+  if (!m.vectors)
+    return set_error(MDS_ERR_INVALID_ARG,
+                     "model was fitted on dissimilarities: use mds_embed_from_sqdist");
   if (n_new == 0) return MDS_OK;
   if (!X || !Y) return set_error(MDS_ERR_INVALID_ARG, "X or Y is NULL");
   if (ldx < m.p) return set_error(MDS_ERR_INVALID_ARG, "ldx < p");
@@ -211,6 +214,73 @@ mds_status mds_embed(const mds_model* h, const void* X, int32_t dt, int64_t n_ne
     default: mode = MODE_F16; break;
   }
   return launch_embed(m, mode, X, dt, n_new, ldx, Y, ldy, reinterpret_cast<hipStream_t>(stream));
+}
+
+mds_status mds_fit_from_sqdist(const double* D1, int64_t l, int64_t ldd, int32_t r, void* stream,
+                               mds_model** out) {
+  if (!out) return set_error(MDS_ERR_INVALID_ARG, "out is NULL");
+  if (!D1) return set_error(MDS_ERR_INVALID_ARG, "D1 is NULL");
+  if (l < 2) return set_error(MDS_ERR_INVALID_ARG, "need l >= 2");
+  if (ldd < l) return set_error(MDS_ERR_INVALID_ARG, "ldd < l");
+  if (r < 1 || r > l - 1 || r > MDS_MAX_R)
+    return set_error(MDS_ERR_INVALID_ARG, "need 1 <= r <= min(l - 1, MDS_MAX_R)");
+  if (l > (int64_t)1 << 16) return set_error(MDS_ERR_INVALID_ARG, "l too large (max 65536)");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  mds_model* h = nullptr;
+  try {
+    h = new mds_model();
+    Model& m = h->m;
+    m.n_fit = l;
+    m.p = 0;
+    m.l = l;
+    m.l_pad = round_up(l, BN);
+    m.r = r;
+    m.rb = (int32_t)((r + 15) / 16);
+    if (m.rb == 3) m.rb = 4;
+    m.vectors = false;
+    (void)hipGetDevice(&m.dev);
+    m.idx_host = new int64_t[(size_t)l];
+    for (int64_t i = 0; i < l; ++i) m.idx_host[i] = i;
+  } catch (const std::bad_alloc&) {
+    if (h) {
+      free_model(h->m);
+      delete h;
+    }
+    return set_error(MDS_ERR_OOM, "host allocation failed");
+  }
+  Model& m = h->m;
+  mds_status s = fit_on_device(m, nullptr, MDS_F64, 0, nullptr, D1, ldd, st);
+  if (s == MDS_OK) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) s = hip_fail(e, "fit synchronize");
+  } else {
+    (void)hipStreamSynchronize(st);
+  }
+  if (s != MDS_OK) {
+    free_model(m);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return MDS_OK;
+}
+
+mds_status mds_embed_from_sqdist(const mds_model* h, const void* A2, int32_t dt, int64_t n_new,
+                                 int64_t lda, int32_t prec, void* Y, int64_t ldy, void* stream) {
+  if (!h) return set_error(MDS_ERR_INVALID_ARG, "model is NULL");
+  const Model& m = h->m;
+  if (n_new < 0) return set_error(MDS_ERR_INVALID_ARG, "n_new < 0");
+  if (prec != MDS_PREC_FP64 && prec != MDS_PREC_FP32)
+    return set_error(MDS_ERR_INVALID_ARG, "embedding from dissimilarities takes FP64 or FP32");
+  if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
+  if (prec == MDS_PREC_FP32 && dt != MDS_F32)
+    return set_error(MDS_ERR_INVALID_ARG, "FP32 precision takes MDS_F32 input");
+  if (n_new == 0) return MDS_OK;
+  if (!A2 || !Y) return set_error(MDS_ERR_INVALID_ARG, "A2 or Y is NULL");
+  if (lda < m.l) return set_error(MDS_ERR_INVALID_ARG, "lda < l");
+  if (ldy < m.r) return set_error(MDS_ERR_INVALID_ARG, "ldy < r");
+  return launch_embed_sqdist(m, prec == MDS_PREC_FP64 ? 1 : 0, A2, dt, n_new, lda, Y, ldy,
+                             reinterpret_cast<hipStream_t>(stream));
 }
 
 void mds_free(mds_model* h) {

@@ -68,8 +68,6 @@ struct Tr<MODE_BF16> {
   using T = float;
   using Acc = f4;
   static constexpr int E = 4;
-  static constexpr int KB = 1;
-  static constexpr int KBLK = 32;
   static constexpr int CH = 32;
 };
 template <>

@@ -118,6 +118,23 @@ __global__ __launch_bounds__(256) void k_sqdist(const double* __restrict__ M, in
     }
 }
 
+// Copy a caller's squared-dissimilarity matrix into Delta1, flagging
+// non-finite entries (flag[0]) and asymmetry (flag[1]); the copy is made
+// exactly symmetric as (d_ij + d_ji) / 2.
+__global__ __launch_bounds__(256) void k_load_sqdist(const double* __restrict__ D1, int64_t ldd,
+                                                     int64_t l, double* __restrict__ D,
+                                                     int* __restrict__ flags) {
+  const int64_t total = l * l;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / l, j = e - (e / l) * l;
+    const double a = D1[i * ldd + j], b = D1[j * ldd + i];
+    if (!isfinite(a)) flags[0] = 1;
+    if (fabs(a - b) > 1e-12 * (fabs(a) + fabs(b))) flags[1] = 1;
+    D[e] = 0.5 * (a + b);
+  }
+}
+
 // ------------------------------------------------------------- centring
 __global__ __launch_bounds__(256) void k_rowmean(const double* __restrict__ D, int64_t l,
                                                  double* __restrict__ d1) {
@@ -617,6 +634,17 @@ __global__ __launch_bounds__(256) void k_bias(const double* __restrict__ M, int6
   }
 }
 
+// q as FP64 and FP32 (zero for padding landmarks), for embedding from
+// dissimilarities
+__global__ void k_copy_q(const double* __restrict__ q, int64_t l, int64_t l_pad,
+                         double* __restrict__ q64, float* __restrict__ q32) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= l_pad) return;
+  const double v = (i < l) ? q[i] : 0.0;
+  q64[i] = v;
+  q32[i] = (float)v;
+}
+
 // FP16 split scale: 2^s with the largest landmark magnitude at 2^12, so data
 // up to 16x larger than every landmark stays below the FP16 maximum.
 __global__ __launch_bounds__(256) void k_scale(const double* __restrict__ rowmax, int64_t l,
@@ -723,7 +751,8 @@ struct Layout {
 }  // namespace
 
 mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int64_t* idx_dev,
-                         hipStream_t st) {
+                         const double* D1, int64_t ldd, hipStream_t st) {
+  const bool vectors = (D1 == nullptr);
   const int64_t l = m.l, p = m.p, l_pad = m.l_pad;
   const int r = m.r;
   const int nch64 = (int)((p + 15) / 16);
@@ -742,6 +771,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   const size_t ow64 = lay.take(sizeof(double) * l_pad * ldw);
   const size_t oc32 = lay.take(sizeof(float) * l_pad);
   const size_t oc64 = lay.take(sizeof(double) * l_pad);
+  const size_t oq32 = lay.take(sizeof(float) * l_pad);
+  const size_t oq64 = lay.take(sizeof(double) * l_pad);
   m.base = model_alloc(m.dev, lay.off);
   if (!m.base) return set_error(MDS_ERR_OOM, "device allocation of the model failed");
   char* b = static_cast<char*>(m.base);
@@ -753,6 +784,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   m.w64 = b + ow64;
   m.c32 = b + oc32;
   m.c64 = b + oc64;
+  m.q32 = b + oq32;
+  m.q64 = b + oq64;
   m.bytes = (int64_t)lay.off;
   MDS_HIP(hipMemsetAsync(m.base, 0, lay.off, st));
 
@@ -796,8 +829,12 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   MDS_HIP(hipMemsetAsync(ctrl, 0, sizeof(int) * 16, st));
   MDS_HIP(hipMemsetAsync(beta, 0, sizeof(double) * (kcap + 1), st));
 
-  // ---- gather, distances, centring ----
-  {
+  // ---- gather, distances (or the caller's matrix), centring ----
+  if (!vectors) {
+    const int grid = (int)std::min<int64_t>((l * l + 255) / 256, 8192);
+    k_load_sqdist<<<grid, 256, 0, st>>>(D1, ldd, l, DQ, ctrl + 3);
+    LAUNCH_CHECK("load dissimilarities");
+  } else {
     const int64_t total = l * p;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
     if (dt == MDS_F32)
@@ -807,10 +844,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
       k_gather<double><<<grid, 256, 0, st>>>((const double*)X, ldx, idx_dev, l, p, ldm,
                                              (double*)m.m64, ctrl + 3);
     LAUNCH_CHECK("gather");
-  }
-  {
-    dim3 grid((unsigned)((l + 63) / 64), (unsigned)((l + 63) / 64));
-    k_sqdist<<<grid, 256, 0, st>>>((const double*)m.m64, ldm, l, p, DQ);
+    dim3 sq_grid((unsigned)((l + 63) / 64), (unsigned)((l + 63) / 64));
+    k_sqdist<<<sq_grid, 256, 0, st>>>((const double*)m.m64, ldm, l, p, DQ);
     LAUNCH_CHECK("sqdist");
   }
   k_rowmean<<<(unsigned)l, 256, 0, st>>>(DQ, l, d1);
@@ -823,7 +858,11 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   MDS_HIP(hipMemcpyAsync(hctrl, ctrl, sizeof(hctrl), hipMemcpyDeviceToHost, st));
   MDS_HIP(hipMemcpyAsync(hscal, scal, sizeof(hscal), hipMemcpyDeviceToHost, st));
   MDS_HIP(hipStreamSynchronize(st));
-  if (hctrl[3]) return set_error(MDS_ERR_INVALID_ARG, "non-finite value in a landmark row");
+  if (hctrl[3])
+    return set_error(MDS_ERR_INVALID_ARG, vectors ? "non-finite value in a landmark row"
+                                                  : "non-finite squared dissimilarity");
+  if (!vectors && hctrl[4]) return set_error(MDS_ERR_INVALID_ARG, "dissimilarity matrix is not symmetric");
+  MDS_HIP(hipMemsetAsync(ctrl + 3, 0, sizeof(int) * 2, st));
   const double qnorm = hscal[1];
   if (!(qnorm > 0.0)) return set_error(MDS_ERR_DEGENERATE, "all landmarks coincide (Q1 = 0)");
 
@@ -961,16 +1000,20 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   MDS_HIP(hipMemcpyAsync(live_dev, live.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
   k_finalize_cols<<<r, 256, 0, st>>>((double*)bVr.p, l, r, theta, live_dev, (double*)bX1.p,
                                      (double*)m.w64, ldw, (float*)m.w32, l_pad);
-  k_bias<<<(unsigned)((l_pad + 3) / 4), 256, 0, st>>>((const double*)m.m64, ldm, l, l_pad, p, q,
+  k_copy_q<<<(unsigned)((l_pad + 255) / 256), 256, 0, st>>>(q, l, l_pad, (double*)m.q64,
+                                                            (float*)m.q32);
+  if (vectors) {
+    k_bias<<<(unsigned)((l_pad + 3) / 4), 256, 0, st>>>((const double*)m.m64, ldm, l, l_pad, p, q,
                                                         (double*)m.c64, (float*)m.c32, rowmax);
-  k_scale<<<1, 256, 0, st>>>(rowmax, l, scales);
-  {
+    k_scale<<<1, 256, 0, st>>>(rowmax, l, scales);
     const int64_t total = l_pad * (int64_t)nch32 * 32;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     k_pack32<<<grid, 256, 0, st>>>((const double*)m.m64, ldm, l_pad, p, nch32, (float*)m.m32,
                                    (uint16_t*)m.mbf, (uint16_t*)m.mh, scales, ctrl + 4);
-    LAUNCH_CHECK("finalise");
+  } else {
+    k_scale<<<1, 256, 0, st>>>(rowmax, 0, scales);  // unused without vectors
   }
+  LAUNCH_CHECK("finalise");
   // ---- host copies ----
   m.lam_host = new double[r];
   m.x1_host = new double[(size_t)l * r];

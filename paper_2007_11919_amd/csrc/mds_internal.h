@@ -75,6 +75,9 @@ struct Model {
   void* w64 = nullptr;    // l_pad x 16rb double
   void* c32 = nullptr;    // l_pad float
   void* c64 = nullptr;    // l_pad double
+  void* q32 = nullptr;    // l_pad float: diag(Q1), for embedding from dissimilarities
+  void* q64 = nullptr;    // l_pad double
+  bool vectors = true;    // fitted on data rows (false: on a dissimilarity matrix)
   int bf_lo_zero = 0, h_lo_zero = 0;
   float h_prescale = 1.f, h_postscale = 1.f;
   int64_t bytes = 0;
@@ -100,12 +103,16 @@ void sample_landmarks_host(int64_t n, int64_t l, uint64_t seed, int64_t* out);
 
 // ---- fit kernels (fit.hip) ------------------------------------------------
 struct FitScratch;
+// D1 == nullptr: fit on the landmark rows of X; otherwise on the caller's
+// l x l squared-dissimilarity matrix D1 (device, leading dimension ldd).
 mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int64_t* idx_dev,
-                         hipStream_t st);
+                         const double* D1, int64_t ldd, hipStream_t st);
 
 // ---- embed kernels (embed.hip) -----------------------------------------
 mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t n, int64_t ldx,
                         void* Y, int64_t ldy, hipStream_t st);
+mds_status launch_embed_sqdist(const Model& m, int prec64, const void* A2, int dt, int64_t n,
+                               int64_t lda, void* Y, int64_t ldy, hipStream_t st);
 // persistent serving launch over a device table of tiles
 // rbc = rb_class(rb): 0 for rb 1, 1 for rb 2, 2 for rb 3..4
 mds_status launch_embed_worklist(int mode, int rbc, const EmbedModelView* views_dev,

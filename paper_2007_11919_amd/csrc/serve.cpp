@@ -367,6 +367,7 @@ mds_status mds_serve_add_model(mds_server* s, const mds_model* h, int32_t* model
   std::lock_guard<std::mutex> lk(s->mu);
   if ((int)s->models.size() >= kMaxModels) return set_error(MDS_ERR_BUDGET, "too many models");
   if (m->rb > embed_max_rb()) return set_error(MDS_ERR_INVALID_ARG, "model r too large for serving");
+  if (!m->vectors) return set_error(MDS_ERR_INVALID_ARG, "serving needs a model fitted on data rows");
   if (s->bytes_in_use + m->bytes > s->budget)
     return set_error(MDS_ERR_BUDGET, "model does not fit in the byte budget");
   const int id = (int)s->models.size();
