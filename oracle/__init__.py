@@ -1,4 +1,4 @@
-"""FP64 CPU oracle of interpolation MDS.
+"""FP64 CPU oracle of interpolation MDS and divide-and-conquer MDS.
 
 TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
 CPU-baseline leg of the benchmark may import or run anything in this
@@ -26,6 +26,7 @@ from .mds import (TAU, DegenerateError, Fit, classical_mds, fit_from_sqdist, fit
                   sqdist_rows, sqdist_rows_expanded, top_eigenpairs)
 from .sampler import SplitMix64, bounded, fisher_yates_prefix, sample_landmarks
 from .linalg_small import jacobi_eigh, procrustes
+from . import dc
 
 __all__ = [
     "TAU", "DegenerateError", "Fit", "classical_mds", "fit_from_sqdist", "fit_landmarks",
@@ -34,5 +35,5 @@ __all__ = [
     "interpolation_mds_paper_layout", "lmds_block", "sign_convention",
     "sqdist_rows", "sqdist_rows_expanded", "top_eigenpairs", "SplitMix64",
     "bounded", "fisher_yates_prefix", "sample_landmarks", "jacobi_eigh",
-    "procrustes",
+    "procrustes", "dc",
 ]
