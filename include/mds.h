@@ -144,6 +144,44 @@ mds_status mds_fit_from_sqdist(const double* D1, int64_t l, int64_t ldd, int32_t
 mds_status mds_embed_from_sqdist(const mds_model* m, const void* A2, int32_t dt, int64_t n_new,
                                  int64_t lda, int32_t prec, void* Y, int64_t ldy, void* stream);
 
+/* ---- divide-and-conquer MDS (Section 3.2) ------------------------------
+ * The rows are split at random into parts that share c connecting points;
+ * classical MDS (Section 2) runs on every part and each part's
+ * configuration is mapped onto the first one by the Procrustes rotation and
+ * shift fitted on the connecting rows.
+ * Partition: row i gets the key SplitMix64(seed) output number i+1 (the
+ * finaliser of seed + (i+1) * 0x9E3779B97F4A7C15); rows are ordered by
+ * (key, index).  The first c rows of that order are the connecting points,
+ * the rest are cut in order into pieces of l - c; part j is the connecting
+ * rows followed by piece j, so there are ceil(1 + (n - l) / (l - c)) parts
+ * (one part holding every row when n <= l), all of l rows but perhaps the
+ * last.  Dissimilarities are squared Euclidean distances between rows.
+ * X:      device, n x p rows, leading dimension ldx >= p, element type dt.
+ * l, c, r: part size, connecting points, output dimension:
+ *         1 <= r <= MDS_MAX_R, c >= r + 1, c < l <= MDS_DC_MAX_L, c < n.
+ * Y:      device, n x r doubles, leading dimension ldy >= r; row i is the
+ *         configuration of row i of X.  The sign of each column of the first
+ *         part's configuration follows the fit's convention (largest-|.|
+ *         entry positive, first row in part order on ties); columns whose
+ *         eigenvalue in the first part is <= MDS_TAU * lambda_1 are zero.
+ *         The Procrustes fit is orthogonal with a shift and no dilation,
+ *         over the live columns.
+ * lam_bar: host, r doubles (may be NULL): (1/parts) sum_j lambda^j / n_j,
+ *         the column-variance estimates of Section 3.2.
+ * r_eff:  host (may be NULL): live columns.
+ * order_out: device, n int64 (may be NULL): the row order (position ->
+ *         row) that defines the parts.
+ * Everything runs in FP64 on `stream`; the call returns when Y is complete.
+ * Errors: INVALID_ARG (pointers, sizes, non-finite X), DEGENERATE (a part
+ * whose rows all coincide, or connecting rows that do not fix the rotation:
+ * smallest singular value of the cross-product matrix <= 1e-9 of the
+ * largest), OOM, HIP. */
+#define MDS_DC_MAX_L 4096
+mds_status mds_divide_conquer(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx,
+                              int64_t l, int64_t c, int32_t r, uint64_t seed, double* Y,
+                              int64_t ldy, double* lam_bar, int32_t* r_eff, int64_t* order_out,
+                              void* stream);
+
 /* Release every device and host buffer of the model.  NULL is a no-op.
  * The caller must ensure no embed on any stream still uses m. */
 void mds_free(mds_model* m);

@@ -220,6 +220,28 @@ def embed_from_sqdist(model, A2, prec="fp32", Y=None, stream=None):
     return Y
 
 
+def divide_conquer(X, l, c, r, seed=0, Y=None, return_order=False, stream=None):
+    """mds_divide_conquer (Section 3.2): divide-and-conquer MDS of the rows
+    of X (n x p device tensor, float32 or float64).  Returns (Y, lam_bar,
+    r_eff), plus the row order defining the parts if return_order."""
+    import torch
+    _check_matrix(X, "X")
+    n, p = X.shape
+    if Y is None:
+        Y = torch.empty((n, r), dtype=torch.float64, device=X.device)
+    order = torch.empty(n, dtype=torch.int64, device=X.device) if return_order else None
+    ldx = X.stride(0) if n > 1 else p
+    ldy = Y.stride(0) if n > 1 else r
+    lam_bar = (ctypes.c_double * r)()
+    r_eff = ctypes.c_int32(0)
+    _check(_lib.lib().mds_divide_conquer(
+        ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n, p, ldx, l, c, r, seed,
+        ctypes.c_void_p(Y.data_ptr()), ldy, lam_bar, ctypes.byref(r_eff),
+        ctypes.c_void_p(order.data_ptr()) if order is not None else None, _stream_ptr(stream)))
+    out = (Y, np.array(lam_bar[:], dtype=np.float64), int(r_eff.value))
+    return out + (order,) if return_order else out
+
+
 def free(model):
     """mds_free."""
     model.free()

@@ -265,6 +265,27 @@ mds_status mds_fit_from_sqdist(const double* D1, int64_t l, int64_t ldd, int32_t
   return MDS_OK;
 }
 
+mds_status mds_divide_conquer(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
+                              int64_t c, int32_t r, uint64_t seed, double* Y, int64_t ldy,
+                              double* lam_bar, int32_t* r_eff, int64_t* order_out, void* stream) {
+  if (!X || !Y) return set_error(MDS_ERR_INVALID_ARG, "X or Y is NULL");
+  if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
+  if (p < 1) return set_error(MDS_ERR_INVALID_ARG, "p must be >= 1");
+  if (p > (int64_t)1 << 24) return set_error(MDS_ERR_INVALID_ARG, "p too large");
+  if (ldx < p) return set_error(MDS_ERR_INVALID_ARG, "ldx < p");
+  if (r < 1 || r > MDS_MAX_R) return set_error(MDS_ERR_INVALID_ARG, "need 1 <= r <= MDS_MAX_R");
+  if (ldy < r) return set_error(MDS_ERR_INVALID_ARG, "ldy < r");
+  if (c < (int64_t)r + 1) return set_error(MDS_ERR_INVALID_ARG, "need c >= r + 1");
+  if (l <= c) return set_error(MDS_ERR_INVALID_ARG, "need l > c");
+  if (l > MDS_DC_MAX_L) return set_error(MDS_ERR_INVALID_ARG, "l too large (max 4096)");
+  if (n <= c) return set_error(MDS_ERR_INVALID_ARG, "need n > c");
+  if (n > ((int64_t)1 << 40)) return set_error(MDS_ERR_INVALID_ARG, "n too large");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  mds_status s = dc_on_device(X, dt, n, p, ldx, l, c, r, seed, Y, ldy, lam_bar, r_eff, order_out, st);
+  if (s != MDS_OK) (void)hipStreamSynchronize(st);
+  return s;
+}
+
 mds_status mds_embed_from_sqdist(const mds_model* h, const void* A2, int32_t dt, int64_t n_new,
                                  int64_t lda, int32_t prec, void* Y, int64_t ldy, void* stream) {
   if (!h) return set_error(MDS_ERR_INVALID_ARG, "model is NULL");

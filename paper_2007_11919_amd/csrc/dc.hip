@@ -1,0 +1,736 @@
+// Divide-and-conquer MDS (Section 3.2) on the GPU, all in FP64.
+//
+//   partition   row i gets the key SplitMix64(seed) output i+1; a radix sort
+//               orders rows by (key, index).  The first c rows of that order
+//               are the connecting points; the rest are cut into consecutive
+//               pieces of l - c.  Part j holds the connecting rows followed
+//               by its own piece, so all parts have l rows except perhaps
+//               the last, and there are ceil(1 + (n - l) / (l - c)) parts.
+//   per part    classical MDS (Section 2): the top r eigenpairs of
+//               Q_j = -1/2 P Delta_j P and X_j = V Lambda^{1/2}.
+//   alignment   every X_j (j >= 1) is mapped onto X_0 by the Procrustes
+//               rotation T_j and shift t_j fitted on the connecting rows;
+//               its own rows become X_j T_j + t_j and are written to their
+//               input positions.
+//
+// For squared Euclidean distances Q_j = B B' with B the centred rows of the
+// part (m x p); B'B (p x p) has the same non-zero eigenvalues, and its unit
+// eigenvectors u give the coordinates X_j = B u.  Each part is solved
+// through whichever Gram matrix is smaller, by a dense symmetric solver in
+// one workgroup: Householder reduction to tridiagonal form (in LDS when the
+// matrix fits), the largest eigenpairs of the tridiagonal matrix by
+// bisection and inverse iteration, and the back-transformation of those
+// vectors.  Every reduction has a fixed order, so a run is reproducible.
+#include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "mds_internal.h"
+#include "tridiag_dev.h"
+
+namespace mds {
+namespace {
+
+struct DcShape {
+  int64_t n, p, l, c;
+  int64_t nparts;
+  int64_t m_max;  // rows of a full part
+  int r;
+};
+
+__host__ __device__ inline int64_t dc_part_size(int64_t j, const DcShape& s) {
+  if (s.nparts == 1) return s.n;
+  const int64_t lo = s.c + j * (s.l - s.c);
+  const int64_t hi = std::min(s.c + (j + 1) * (s.l - s.c), s.n);
+  return s.c + (hi - lo);
+}
+
+// position in the sorted order of row i of part j
+__device__ inline int64_t dc_pos(int64_t j, int64_t i, const DcShape& s) {
+  return i < s.c ? i : s.c + j * (s.l - s.c) + (i - s.c);
+}
+
+// ------------------------------------------------------------- partition
+__global__ void k_dc_keys(int64_t n, uint64_t seed, uint64_t* __restrict__ keys,
+                          int64_t* __restrict__ vals) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    // SplitMix64: the state after i+1 steps is seed + (i+1) * gamma
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    keys[i] = z ^ (z >> 31);
+    vals[i] = i;
+  }
+}
+
+// ----------------------------------------------------------- part means
+// mean[j][k] over the rows of part j, in row order; flags non-finite input.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_dc_mean(const TX* __restrict__ X, int64_t ldx,
+                                                 const int64_t* __restrict__ order, DcShape s,
+                                                 double* __restrict__ mean, int* __restrict__ bad) {
+  const int64_t j = blockIdx.x;
+  const int64_t k = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (k >= s.p) return;
+  const int64_t m = dc_part_size(j, s);
+  double acc = 0.0;
+  bool fin = true;
+  for (int64_t i = 0; i < m; ++i) {
+    const double v = (double)X[order[dc_pos(j, i, s)] * ldx + k];
+    fin = fin && isfinite(v);
+    acc += v;
+  }
+  mean[j * s.p + k] = acc / (double)m;
+  if (!fin) bad[0] = 1;
+}
+
+// -------------------------------------------------------- Gram matrices
+// B'B of a part (p x p): G[a][b] = sum_i (x_ia - mu_a)(x_ib - mu_b) over the
+// part's rows in order.  64x64 tile per block, 4x4 per thread, rows staged
+// 16 at a time.  G[a][b] and G[b][a] are the same sums of the same products,
+// so the result is exactly symmetric.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_dc_gram_feat(const TX* __restrict__ X, int64_t ldx,
+                                                      const int64_t* __restrict__ order, DcShape s,
+                                                      const double* __restrict__ mean, int64_t j0,
+                                                      double* __restrict__ G) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  const int64_t j = j0 + blockIdx.z;
+  const int64_t a0 = (int64_t)blockIdx.y * 64, b0 = (int64_t)blockIdx.x * 64;
+  const int64_t m = dc_part_size(j, s);
+  const double* mu = mean + j * s.p;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int64_t i0 = 0; i0 < m; i0 += 16) {
+    for (int e = t; e < 16 * 64; e += 256) {
+      const int ii = e >> 6, cc = e & 63;
+      const int64_t i = i0 + ii;
+      double va = 0.0, vb = 0.0;
+      if (i < m) {
+        const TX* row = X + order[dc_pos(j, i, s)] * ldx;
+        if (a0 + cc < s.p) va = (double)row[a0 + cc] - mu[a0 + cc];
+        if (b0 + cc < s.p) vb = (double)row[b0 + cc] - mu[b0 + cc];
+      }
+      As[ii][cc] = va;
+      Bs[ii][cc] = vb;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = As[kk][ty + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][tx + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  double* Gp = G + (int64_t)blockIdx.z * s.p * s.p;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t a = a0 + ty + 16 * u, b = b0 + tx + 16 * v;
+      if (a < s.p && b < s.p) Gp[a * s.p + b] = acc[u][v];
+    }
+}
+
+// B B' of a part (m x m, leading dimension m_max): G[i][i'] =
+// sum_k (x_ik - mu_k)(x_i'k - mu_k), features staged 16 at a time.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_dc_gram_rows(const TX* __restrict__ X, int64_t ldx,
+                                                      const int64_t* __restrict__ order, DcShape s,
+                                                      const double* __restrict__ mean, int64_t j0,
+                                                      double* __restrict__ G) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  const int64_t j = j0 + blockIdx.z;
+  const int64_t i0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64;
+  const int64_t m = dc_part_size(j, s);
+  const int64_t ld = s.m_max;
+  if (i0 >= m || k0 >= m) return;
+  const double* mu = mean + j * s.p;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int64_t f0 = 0; f0 < s.p; f0 += 16) {
+    for (int e = t; e < 16 * 64; e += 256) {
+      const int rr = e >> 4, ff = e & 15;
+      const int64_t f = f0 + ff;
+      double va = 0.0, vb = 0.0;
+      if (f < s.p) {
+        if (i0 + rr < m) va = (double)X[order[dc_pos(j, i0 + rr, s)] * ldx + f] - mu[f];
+        if (k0 + rr < m) vb = (double)X[order[dc_pos(j, k0 + rr, s)] * ldx + f] - mu[f];
+      }
+      As[ff][rr] = va;
+      Bs[ff][rr] = vb;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = As[kk][ty + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][tx + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  double* Gp = G + (int64_t)blockIdx.z * ld * ld;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t a = i0 + ty + 16 * u, b = k0 + tx + 16 * v;
+      if (a < m && b < m) Gp[a * ld + b] = acc[u][v];
+    }
+}
+
+// ------------------------------------------------------- dense eigensolver
+// One block per part.  The symmetric matrix (dd x dd, full storage) is
+// reduced to tridiagonal form by Householder reflections H_k = I - tau_k v v'
+// (LAPACK's unblocked lower reduction); v_k is kept in row k, which later
+// steps no longer read.  The nr largest eigenpairs of the tridiagonal matrix
+// are mapped back by z <- H_0 ... H_{dd-3} z.  With IN_LDS the matrix is
+// copied to LDS; otherwise it is reduced in place in global memory.
+//
+// Output per part j: lam[j][t]; for the feature Gram (rows_gram == 0) the
+// eigenvectors U[j] (p x r, row-major); for the row Gram the coordinates
+// Xs[j][i][t] = v_t[i] sqrt(lam_t) (zero where lam_t <= 0).  status[j] = 1
+// when lam_1 <= 0 (all rows of the part coincide).
+template <bool IN_LDS>
+__global__ __launch_bounds__(256) void k_dc_eigen(double* __restrict__ G, int d, DcShape s,
+                                                  int rows_gram, int64_t j0, int nr,
+                                                  double* __restrict__ zg, double* __restrict__ wkg,
+                                                  double* __restrict__ lam, double* __restrict__ U,
+                                                  double* __restrict__ Xs, int* __restrict__ status) {
+  extern __shared__ double dsm[];
+  __shared__ double sh4[4];
+  __shared__ double theta[MDS_MAX_R];
+  const int t = threadIdx.x;
+  const int64_t jc = blockIdx.x, j = j0 + jc;
+  const int dd = rows_gram ? (int)dc_part_size(j, s) : d;
+  const int nrr = std::min(nr, dd);
+  double* Gp = G + jc * (int64_t)d * d;
+  int lda, ldz;
+  double *A, *al, *be, *tau, *pw, *Z, *wk;
+  if (IN_LDS) {
+    lda = dd;
+    ldz = dd;
+    A = dsm;
+    al = A + (int64_t)dd * dd;
+    be = al + dd;
+    tau = be + dd;
+    pw = tau + dd;
+    Z = pw + dd;
+    wk = Z + (int64_t)nr * dd;
+    for (int64_t e = t; e < (int64_t)dd * dd; e += 256) A[e] = Gp[(e / dd) * d + (e % dd)];
+  } else {
+    lda = d;
+    ldz = d;
+    A = Gp;
+    al = dsm;
+    be = al + dd;
+    tau = be + dd;
+    pw = tau + dd;
+    Z = zg + jc * (int64_t)nr * d;
+    wk = wkg + jc * (int64_t)4 * d * nr;
+  }
+  __syncthreads();
+
+  for (int k = 0; k + 2 < dd; ++k) {
+    const int n2 = dd - k - 1;
+    double* rowk = A + (int64_t)k * lda + (k + 1);  // column k below the diagonal, by symmetry
+    double part = 0.0;
+    for (int i = 1 + t; i < n2; i += 256) part = fma(rowk[i], rowk[i], part);
+    const double sigma = block_sum4(part, sh4);
+    const double x0 = rowk[0];
+    if (t == 0) al[k] = A[(int64_t)k * lda + k];
+    if (sigma == 0.0) {  // already tridiagonal in this column: H_k = I
+      if (t == 0) {
+        tau[k] = 0.0;
+        be[k] = x0;
+      }
+      continue;
+    }
+    const double beta = -copysign(sqrt(x0 * x0 + sigma), x0);
+    const double tk = (beta - x0) / beta;
+    const double scale = 1.0 / (x0 - beta);
+    __syncthreads();  // x0 is read by every thread before row k is rewritten
+    for (int i = 1 + t; i < n2; i += 256) rowk[i] *= scale;
+    if (t == 0) {
+      rowk[0] = 1.0;
+      tau[k] = tk;
+      be[k] = beta;
+    }
+    __syncthreads();
+    // p = tau A22 v, reading columns of the symmetric trailing block
+    double* A22 = A + (int64_t)(k + 1) * lda + (k + 1);
+    for (int i = t; i < n2; i += 256) {
+      double acc = 0.0;
+      for (int jj = 0; jj < n2; ++jj) acc = fma(A22[(int64_t)jj * lda + i], rowk[jj], acc);
+      pw[i] = tk * acc;
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = t; i < n2; i += 256) pv = fma(pw[i], rowk[i], pv);
+    const double K = 0.5 * tk * block_sum4(pv, sh4);
+    for (int i = t; i < n2; i += 256) pw[i] = pw[i] - K * rowk[i];  // w
+    __syncthreads();
+    // A22 -= v w' + w v'; both products are rounded before the sum, so the
+    // update keeps A22 exactly symmetric
+    for (int64_t e = t; e < (int64_t)n2 * n2; e += 256) {
+      const int i = (int)(e / n2), jj = (int)(e % n2);
+      A22[(int64_t)i * lda + jj] -= __dmul_rn(rowk[i], pw[jj]) + __dmul_rn(pw[i], rowk[jj]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (dd >= 2) {
+      al[dd - 2] = A[(int64_t)(dd - 2) * lda + (dd - 2)];
+      be[dd - 2] = A[(int64_t)(dd - 1) * lda + (dd - 2)];
+      tau[dd - 2] = 0.0;
+    }
+    al[dd - 1] = A[(int64_t)(dd - 1) * lda + (dd - 1)];
+  }
+  __syncthreads();
+
+  tridiag_top(al, be, dd, nrr, theta, Z, ldz, wk);
+  __syncthreads();
+
+  // back-transformation; wave w owns vectors w, w+4, ...
+  const int wv = t >> 6, lane = t & 63;
+  for (int k = dd - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    const double* v = A + (int64_t)k * lda + (k + 1);
+    const int n2 = dd - k - 1;
+    for (int tt = wv; tt < nrr; tt += 4) {
+      double* z = Z + (int64_t)tt * ldz + (k + 1);
+      double dot = 0.0;
+      for (int i = lane; i < n2; i += 64) dot = fma(v[i], z[i], dot);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+      const double f = tk * dot;
+      for (int i = lane; i < n2; i += 64) z[i] -= f * v[i];
+    }
+    if (!IN_LDS) __threadfence_block();
+  }
+  __syncthreads();
+
+  for (int tt = t; tt < s.r; tt += 256) lam[j * s.r + tt] = tt < nrr ? theta[tt] : 0.0;
+  if (t == 0) status[j] = (nrr > 0 && theta[0] > 0.0) ? 0 : 1;
+  if (!rows_gram) {
+    for (int64_t e = t; e < (int64_t)dd * s.r; e += 256) {
+      const int i = (int)(e / s.r), tt = (int)(e % s.r);
+      U[(j * d + i) * s.r + tt] = tt < nrr ? Z[(int64_t)tt * ldz + i] : 0.0;
+    }
+  } else {
+    for (int64_t e = t; e < (int64_t)dd * s.r; e += 256) {
+      const int i = (int)(e / s.r), tt = (int)(e % s.r);
+      double v = 0.0;
+      if (tt < nrr && theta[tt] > 0.0) v = Z[(int64_t)tt * ldz + i] * sqrt(theta[tt]);
+      Xs[(j * s.m_max + i) * s.r + tt] = v;
+    }
+  }
+}
+
+// ---------------------------------------------- coordinates X_j = B u
+// Block: 64 rows of one part; features staged 32 at a time with U's rows.
+// Thread (row rl, group g) owns columns g, g+4, ..., in a fixed order.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_dc_coords(const TX* __restrict__ X, int64_t ldx,
+                                                   const int64_t* __restrict__ order, DcShape s,
+                                                   const double* __restrict__ mean,
+                                                   const double* __restrict__ U,
+                                                   double* __restrict__ Xs) {
+  __shared__ double Xt[64][33];
+  __shared__ double Ut[32][MDS_MAX_R + 1];
+  const int t = threadIdx.x;
+  const int rl = t & 63, g = t >> 6;
+  const int64_t j = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t m = dc_part_size(j, s);
+  if (i0 >= m) return;
+  const double* mu = mean + j * s.p;
+  const double* Uj = U + j * s.p * s.r;
+  double acc[MDS_MAX_R / 4];
+#pragma unroll
+  for (int u = 0; u < MDS_MAX_R / 4; ++u) acc[u] = 0.0;
+  for (int64_t f0 = 0; f0 < s.p; f0 += 32) {
+    for (int e = t; e < 64 * 32; e += 256) {
+      const int rr = e >> 5, ff = e & 31;
+      const int64_t i = i0 + rr, f = f0 + ff;
+      Xt[rr][ff] = (i < m && f < s.p) ? (double)X[order[dc_pos(j, i, s)] * ldx + f] - mu[f] : 0.0;
+    }
+    for (int e = t; e < 32 * s.r; e += 256) {
+      const int ff = e / s.r, tt = e % s.r;
+      Ut[ff][tt] = (f0 + ff < s.p) ? Uj[(f0 + ff) * s.r + tt] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MDS_MAX_R / 4; ++u) {
+      const int tt = g + 4 * u;
+      if (tt < s.r) {
+        double a = acc[u];
+        for (int ff = 0; ff < 32; ++ff) a = fma(Xt[rl][ff], Ut[ff][tt], a);
+        acc[u] = a;
+      }
+    }
+    __syncthreads();
+  }
+  if (i0 + rl < m) {
+#pragma unroll
+    for (int u = 0; u < MDS_MAX_R / 4; ++u) {
+      const int tt = g + 4 * u;
+      if (tt < s.r) Xs[(j * s.m_max + i0 + rl) * s.r + tt] = acc[u];
+    }
+  }
+}
+
+// ------------------------------------------------------------- alignment
+// One block per part.  Part 0: the sign of each live column is fixed
+// (largest-|.| entry positive, first row on ties) and its rows are written.
+// Part j >= 1: Procrustes fit on the c connecting rows over the r0 live
+// columns: C = (B - 1b')'(A - 1a') (B: part j, A: part 0), C = U S W' by
+// one-sided Jacobi (Hestenes) in one wave, T = U W', t = a - T' b; own rows
+// become X_j T + t.  Columns r0..r-1 are zero.  status[j] = 2 when the
+// smallest singular value of C is <= 1e-9 of the largest.
+__global__ __launch_bounds__(256) void k_dc_align(const double* __restrict__ Xs,
+                                                  const int64_t* __restrict__ order, DcShape s,
+                                                  int r0, double* __restrict__ Y, int64_t ldy,
+                                                  int* __restrict__ status) {
+  extern __shared__ double dyn[];
+  __shared__ double sgn[MDS_MAX_R];
+  __shared__ double amean[MDS_MAX_R], bmean[MDS_MAX_R], tv[MDS_MAX_R], sig[MDS_MAX_R];
+  // three r0 x r0 matrices, rows padded to r0 + 1:
+  // CS(col, row) of C (then of C J), JS(col, row) of J, TS(a, k) = T[a][k]
+  const int ldr = r0 + 1;
+  double* cs_m = dyn;
+  double* js_m = cs_m + (size_t)r0 * ldr;
+  double* ts_m = js_m + (size_t)r0 * ldr;
+#define CS(a, b) cs_m[(a) * ldr + (b)]
+#define JS(a, b) js_m[(a) * ldr + (b)]
+#define TS(a, b) ts_m[(a) * ldr + (b)]
+  const int t = threadIdx.x;
+  const int64_t j = blockIdx.x;
+  const int r = s.r;
+  const double* X0 = Xs;
+  const double* Xj = Xs + j * s.m_max * r;
+  const int64_t m0 = dc_part_size(0, s);
+  if (t < r0) {
+    double best = -1.0, val = 0.0;
+    for (int64_t i = 0; i < m0; ++i) {
+      const double v = X0[i * r + t];
+      if (fabs(v) > best) {
+        best = fabs(v);
+        val = v;
+      }
+    }
+    sgn[t] = val < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  if (j == 0) {
+    for (int64_t e = t; e < m0 * r; e += 256) {
+      const int64_t i = e / r;
+      const int k = (int)(e % r);
+      Y[order[dc_pos(0, i, s)] * ldy + k] = k < r0 ? sgn[k] * X0[i * r + k] : 0.0;
+    }
+    return;
+  }
+  const int64_t c = s.c;
+  if (t < r0) {
+    double sa = 0.0, sb = 0.0;
+    for (int64_t i = 0; i < c; ++i) {
+      sa += sgn[t] * X0[i * r + t];
+      sb += Xj[i * r + t];
+    }
+    amean[t] = sa / (double)c;
+    bmean[t] = sb / (double)c;
+  }
+  __syncthreads();
+  for (int e = t; e < r0 * r0; e += 256) {
+    const int a = e / r0, b = e % r0;  // C[a][b]
+    double acc = 0.0;
+    for (int64_t i = 0; i < c; ++i)
+      acc = fma(Xj[i * r + a] - bmean[a], sgn[b] * X0[i * r + b] - amean[b], acc);
+    CS(b, a) = acc;
+    JS(b, a) = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (t < 64) {
+    const int lane = t;
+    const bool own = lane < r0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      int rotated = 0;
+      for (int b1 = 0; b1 + 1 < r0; ++b1) {
+        for (int b2 = b1 + 1; b2 < r0; ++b2) {
+          const double x1 = own ? CS(b1, lane) : 0.0;
+          const double x2 = own ? CS(b2, lane) : 0.0;
+          double al = x1 * x1, be = x2 * x2, ga = x1 * x2;
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+            al += __shfl_xor(al, off, 64);
+            be += __shfl_xor(be, off, 64);
+            ga += __shfl_xor(ga, off, 64);
+          }
+          if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tn = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tn * tn);
+          const double sn = cs * tn;
+          ++rotated;
+          if (own) {
+            CS(b1, lane) = cs * x1 - sn * x2;
+            CS(b2, lane) = sn * x1 + cs * x2;
+            const double j1 = JS(b1, lane), j2 = JS(b2, lane);
+            JS(b1, lane) = cs * j1 - sn * j2;
+            JS(b2, lane) = sn * j1 + cs * j2;
+          }
+        }
+      }
+      if (rotated == 0) break;
+    }
+    for (int b = 0; b < r0; ++b) {
+      const double x = own ? CS(b, lane) : 0.0;
+      double nn = x * x;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
+      if (lane == 0) sig[b] = sqrt(nn);
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    double smax = 0.0, smin = INFINITY;
+    for (int b = 0; b < r0; ++b) {
+      smax = fmax(smax, sig[b]);
+      smin = fmin(smin, sig[b]);
+    }
+    status[j] = (smin > 1e-9 * smax) ? 0 : 2;
+  }
+  for (int e = t; e < r0 * r0; e += 256) {
+    const int a = e / r0, k = e % r0;
+    double acc = 0.0;
+    for (int b = 0; b < r0; ++b) acc = fma(CS(b, a) / sig[b], JS(b, k), acc);
+    TS(a, k) = acc;
+  }
+  __syncthreads();
+  if (t < r0) {
+    double acc = 0.0;
+    for (int a = 0; a < r0; ++a) acc = fma(TS(a, t), bmean[a], acc);
+    tv[t] = amean[t] - acc;
+  }
+  __syncthreads();
+  const int64_t m = dc_part_size(j, s);
+  for (int64_t e = t; e < (m - c) * r; e += 256) {
+    const int64_t i = c + e / r;
+    const int k = (int)(e % r);
+    double y = 0.0;
+    if (k < r0) {
+      double acc = 0.0;
+      for (int a = 0; a < r0; ++a) acc = fma(Xj[i * r + a], TS(a, k), acc);
+      y = acc + tv[k];
+    }
+    Y[order[dc_pos(j, i, s)] * ldy + k] = y;
+  }
+}
+
+#undef CS
+#undef JS
+#undef TS
+
+struct DevMem {
+  void* p = nullptr;
+  hipStream_t st = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFreeAsync(p, st);
+  }
+  template <typename T>
+  T* get() const {
+    return static_cast<T*>(p);
+  }
+};
+
+#define DC_HIP(call)                                     \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) return hip_fail(_e, #call);    \
+  } while (0)
+
+#define DC_LAUNCH(what)                                  \
+  do {                                                   \
+    hipError_t _e = hipGetLastError();                   \
+    if (_e != hipSuccess) return hip_fail(_e, what);     \
+  } while (0)
+
+constexpr size_t kDcLdsMax = 150 * 1024;
+constexpr size_t kDcGramBudget = (size_t)1 << 30;
+
+size_t eigen_lds_bytes(int d, int nr) {
+  // A, four vectors, Z and the inverse-iteration work
+  return sizeof(double) * ((size_t)d * d + 4 * (size_t)d + (size_t)nr * d + 4 * (size_t)d * nr);
+}
+
+template <typename TX>
+mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y, int64_t ldy,
+                  double* lam_bar, int32_t* r_eff, int64_t* order_out, hipStream_t st) {
+  const int64_t n = s.n, p = s.p, np = s.nparts;
+  const int r = s.r;
+  const bool rows_gram = s.m_max < p;  // solve through the smaller Gram matrix
+  const int d = (int)(rows_gram ? s.m_max : p);
+  const int nr = std::min(r, d);
+  const bool in_lds = eigen_lds_bytes(d, nr) <= kDcLdsMax;
+  const int64_t chunk =
+      std::max<int64_t>(1, std::min<int64_t>(np, (int64_t)(kDcGramBudget / (sizeof(double) * (size_t)d * d))));
+
+  DevMem keys_in, keys_out, vals, order_buf, tmp, mean, lam, status, U, Xs, G, zg, wkg, bad;
+  auto alloc = [&](DevMem& b, size_t bytes) -> hipError_t {
+    b.st = st;
+    return hipMallocAsync(&b.p, std::max<size_t>(bytes, 256), st);
+  };
+  DC_HIP(alloc(keys_in, sizeof(uint64_t) * n));
+  DC_HIP(alloc(keys_out, sizeof(uint64_t) * n));
+  DC_HIP(alloc(vals, sizeof(int64_t) * n));
+  int64_t* order = order_out;
+  if (!order) {
+    DC_HIP(alloc(order_buf, sizeof(int64_t) * n));
+    order = order_buf.get<int64_t>();
+  }
+  DC_HIP(alloc(mean, sizeof(double) * np * p));
+  DC_HIP(alloc(lam, sizeof(double) * np * r));
+  DC_HIP(alloc(status, sizeof(int) * np));
+  if (!rows_gram) DC_HIP(alloc(U, sizeof(double) * np * p * r));
+  DC_HIP(alloc(Xs, sizeof(double) * np * s.m_max * r));
+  DC_HIP(alloc(G, sizeof(double) * chunk * d * d));
+  if (!in_lds) {
+    DC_HIP(alloc(zg, sizeof(double) * chunk * nr * d));
+    DC_HIP(alloc(wkg, sizeof(double) * chunk * 4 * d * nr));
+  }
+  DC_HIP(alloc(bad, sizeof(int)));
+  DC_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+
+  // partition: keys, then a stable radix sort of (key, row)
+  {
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    k_dc_keys<<<grid, 256, 0, st>>>(n, seed, keys_in.get<uint64_t>(), vals.get<int64_t>());
+    DC_LAUNCH("partition keys");
+    size_t tbytes = 0;
+    DC_HIP(rocprim::radix_sort_pairs(nullptr, tbytes, keys_in.get<uint64_t>(), keys_out.get<uint64_t>(),
+                                     vals.get<int64_t>(), order, (size_t)n, 0, 64, st));
+    DC_HIP(alloc(tmp, tbytes));
+    DC_HIP(rocprim::radix_sort_pairs(tmp.p, tbytes, keys_in.get<uint64_t>(), keys_out.get<uint64_t>(),
+                                     vals.get<int64_t>(), order, (size_t)n, 0, 64, st));
+  }
+  {
+    dim3 grid((unsigned)np, (unsigned)((p + 255) / 256));
+    k_dc_mean<TX><<<grid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), bad.get<int>());
+    DC_LAUNCH("part means");
+  }
+  static bool attr_set = false;
+  if (!attr_set) {
+    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
+    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
+    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_align),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
+    attr_set = true;
+  }
+  for (int64_t j0 = 0; j0 < np; j0 += chunk) {
+    const int64_t cnt = std::min(chunk, np - j0);
+    const unsigned tiles = (unsigned)((d + 63) / 64);
+    dim3 ggrid(tiles, tiles, (unsigned)cnt);
+    if (rows_gram)
+      k_dc_gram_rows<TX><<<ggrid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), j0, G.get<double>());
+    else
+      k_dc_gram_feat<TX><<<ggrid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), j0, G.get<double>());
+    DC_LAUNCH("part Gram matrices");
+    if (in_lds)
+      k_dc_eigen<true><<<(unsigned)cnt, 256, eigen_lds_bytes(d, nr), st>>>(
+          G.get<double>(), d, s, rows_gram ? 1 : 0, j0, nr, nullptr, nullptr, lam.get<double>(),
+          U.get<double>(), Xs.get<double>(), status.get<int>());
+    else
+      k_dc_eigen<false><<<(unsigned)cnt, 256, sizeof(double) * 4 * (size_t)d, st>>>(
+          G.get<double>(), d, s, rows_gram ? 1 : 0, j0, nr, zg.get<double>(), wkg.get<double>(),
+          lam.get<double>(), U.get<double>(), Xs.get<double>(), status.get<int>());
+    DC_LAUNCH("part eigensolver");
+  }
+  if (!rows_gram) {
+    dim3 grid((unsigned)((s.m_max + 63) / 64), (unsigned)np);
+    k_dc_coords<TX><<<grid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), U.get<double>(),
+                                         Xs.get<double>());
+    DC_LAUNCH("part coordinates");
+  }
+  std::vector<double> hlam((size_t)np * r);
+  std::vector<int> hstat((size_t)np);
+  int hbad = 0;
+  DC_HIP(hipMemcpyAsync(hlam.data(), lam.p, sizeof(double) * np * r, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(hstat.data(), status.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  if (hbad) return set_error(MDS_ERR_INVALID_ARG, "non-finite value in X");
+  for (int64_t j = 0; j < np; ++j)
+    if (hstat[j]) return set_error(MDS_ERR_DEGENERATE, "all rows of a part coincide (lambda_1 <= 0)");
+  int r0 = 0;
+  for (int t = 0; t < r; ++t)
+    if (hlam[t] > MDS_TAU * hlam[0]) ++r0;
+  const size_t align_lds = sizeof(double) * 3 * (size_t)r0 * (r0 + 1);
+  k_dc_align<<<(unsigned)np, 256, align_lds, st>>>(Xs.get<double>(), order, s, r0, Y, ldy,
+                                                   status.get<int>());
+  DC_LAUNCH("alignment");
+  DC_HIP(hipMemcpyAsync(hstat.data(), status.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  for (int64_t j = 1; j < np; ++j)
+    if (hstat[j]) return set_error(MDS_ERR_DEGENERATE, "connecting points do not fix the Procrustes rotation");
+  if (lam_bar) {
+    for (int t = 0; t < r; ++t) {
+      double acc = 0.0;
+      for (int64_t j = 0; j < np; ++j) acc += hlam[(size_t)j * r + t] / (double)dc_part_size(j, s);
+      lam_bar[t] = acc / (double)np;
+    }
+  }
+  if (r_eff) *r_eff = r0;
+  return MDS_OK;
+}
+
+}  // namespace
+
+mds_status dc_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int64_t c,
+                        int r, uint64_t seed, double* Y, int64_t ldy, double* lam_bar, int32_t* r_eff,
+                        int64_t* order_out, hipStream_t st) {
+  DcShape s;
+  s.n = n;
+  s.p = p;
+  s.l = l;
+  s.c = c;
+  s.r = r;
+  s.nparts = (n <= l) ? 1 : 1 + (n - l + (l - c) - 1) / (l - c);
+  s.m_max = std::min(n, l);
+  if (dt == MDS_F32)
+    return dc_run<float>(static_cast<const float*>(X), ldx, s, seed, Y, ldy, lam_bar, r_eff, order_out, st);
+  return dc_run<double>(static_cast<const double*>(X), ldx, s, seed, Y, ldy, lam_bar, r_eff, order_out, st);
+}
+
+}  // namespace mds

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "mds_internal.h"
+#include "tridiag_dev.h"
 
 namespace mds {
 
@@ -40,16 +41,6 @@ __device__ inline double block_sum(double v, double* sh) {
   double r = sh[0];
   __syncthreads();
   return r;
-}
-
-__device__ inline double hash_unit(uint64_t i, uint64_t salt) {
-  // SplitMix64 finaliser of (salt, i) mapped to [-1, 1); used only to seed
-  // the Lanczos start vector and restarts.
-  uint64_t z = i * 0x9E3779B97F4A7C15ull + salt * 0xD1B54A32D192ED03ull + 0x632BE59BD9B4E019ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
 // ---------------------------------------------------------------- gather
@@ -193,18 +184,6 @@ __global__ void k_fill_random(double* __restrict__ w, int64_t l, uint64_t salt) 
   if (i < l) w[i] = hash_unit((uint64_t)i, salt);
 }
 
-// fixed-order sum over a 256-thread block: butterfly within each wave, then
-// the four wave partials in order
-__device__ inline double block_sum4(double v, double* sh4) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = v;
-  __syncthreads();
-  const double r = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
-  __syncthreads();
-  return r;
-}
-
 // w = Q v, one block per row
 __global__ __launch_bounds__(256) void k_symv(const double* __restrict__ Q, int64_t l,
                                               const double* __restrict__ v,
@@ -321,21 +300,6 @@ __global__ __launch_bounds__(1024) void k_set_column(double* __restrict__ V, int
 // Output: theta[t], bound[t] = |beta[k-1] * s_{k-1,t}| (Lanczos residual
 // norm of Ritz pair t), S[t*ldS + i], and kout[0] = k.
 
-__device__ int sturm_count(const double* alpha, const double* beta, int k, double x, double pivmin) {
-  // number of eigenvalues of T below x
-  int cnt = 0;
-  double d = alpha[0] - x;
-  if (fabs(d) < pivmin) d = -pivmin;
-  if (d < 0) ++cnt;
-  for (int i = 1; i < k; ++i) {
-    const double b = beta[i - 1];
-    d = (alpha[i] - x) - b * b / d;
-    if (fabs(d) < pivmin) d = -pivmin;
-    if (d < 0) ++cnt;
-  }
-  return cnt;
-}
-
 __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alpha,
                                                  const double* __restrict__ beta,
                                                  const int* __restrict__ ctrl, int k_host, int r,
@@ -345,10 +309,7 @@ __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alph
                                                  double* __restrict__ gwork, int* __restrict__ kout,
                                                  int work_in_lds) {
   extern __shared__ double sm[];
-  __shared__ double sh[256];
-  __shared__ double sh4[4];
-  __shared__ double ga[MDS_MAX_R], gb[MDS_MAX_R], theta[MDS_MAX_R];
-  __shared__ int flag[256];
+  __shared__ double theta[MDS_MAX_R];
   const int t = threadIdx.x;
   const int k = ctrl[0] ? ctrl[1] + 1 : k_host;
   const int nr = min(r, k);
@@ -359,180 +320,8 @@ __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alph
     be[i] = beta[i];
   }
   __syncthreads();
-  // Gershgorin interval and scale
-  double lo = DBL_MAX, hi = -DBL_MAX, bmax = 0.0;
-  for (int i = t; i < k; i += 256) {
-    const double bl = (i > 0) ? fabs(be[i - 1]) : 0.0;
-    const double br = (i < k - 1) ? fabs(be[i]) : 0.0;
-    lo = fmin(lo, al[i] - bl - br);
-    hi = fmax(hi, al[i] + bl + br);
-    bmax = fmax(bmax, br);
-  }
-  sh[t] = lo;
-  __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
-    if (t < s2) sh[t] = fmin(sh[t], sh[t + s2]);
-    __syncthreads();
-  }
-  lo = sh[0];
-  __syncthreads();
-  sh[t] = hi;
-  __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
-    if (t < s2) sh[t] = fmax(sh[t], sh[t + s2]);
-    __syncthreads();
-  }
-  hi = sh[0];
-  __syncthreads();
-  sh[t] = bmax;
-  __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
-    if (t < s2) sh[t] = fmax(sh[t], sh[t + s2]);
-    __syncthreads();
-  }
-  bmax = sh[0];
-  __syncthreads();
-  const double tnorm = fmax(fabs(lo), fabs(hi));
-  const double pivmin = DBL_MIN * fmax(1.0, bmax * bmax);
-  const double eps = DBL_EPSILON;
-  lo -= 2.0 * eps * tnorm + pivmin;
-  hi += 2.0 * eps * tnorm + pivmin;
-
-  // All wanted eigenvalues at once: a group of G threads multisects each.
-  int G = 256;
-  while (G > 1 && G * nr > 256) G >>= 1;
-  const int grp = t / G, gl = t % G;
-  const bool active = grp < nr;
-  if (t < nr) {
-    ga[t] = lo;
-    gb[t] = hi;
-  }
-  __syncthreads();
-  const int m = k - 1 - grp;  // ascending index of eigenvalue grp (largest first)
-  for (int round = 0; round < 64; ++round) {
-    int more = 0;
-    if (active) {
-      const double a = ga[grp], b = gb[grp];
-      more = (b - a > 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin) ? 1 : 0;
-      if (more) {
-        const double x = a + (b - a) * (double)(gl + 1) / (double)(G + 1);
-        flag[t] = sturm_count(al, be, k, x, pivmin) >= m + 1;
-      }
-    }
-    if (!__syncthreads_or(more)) break;
-    if (active && gl == 0) {
-      const double a = ga[grp], b = gb[grp];
-      if (b - a > 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin) {
-        int first = G;
-        for (int q = 0; q < G; ++q)
-          if (flag[grp * G + q]) {
-            first = q;
-            break;
-          }
-        const double xa = (first == 0) ? a : a + (b - a) * (double)first / (double)(G + 1);
-        const double xb = (first == G) ? b : a + (b - a) * (double)(first + 1) / (double)(G + 1);
-        ga[grp] = xa;
-        gb[grp] = xb;
-      }
-    }
-    __syncthreads();
-  }
-  if (t < nr) theta[t] = 0.5 * (ga[t] + gb[t]);
-  __syncthreads();
-
-  // eigenvectors by inverse iteration (thread tt owns vector tt)
-  const double pert = eps * fmax(tnorm, DBL_MIN) + pivmin;
-  const double cluster_gap = 1e-3 * tnorm;
   double* wk = work_in_lds ? (sm + 2 * k) : gwork;  // [4 arrays][k][nr]
-  for (int it = 0; it < 3; ++it) {
-    if (t < nr) {
-      double* z = S + (int64_t)t * ldS;
-      const double th = theta[t];
-      // factor T - th I with partial pivoting, applying the row operations to
-      // the right-hand side on the fly; keep U (dd, u1, u2) and the
-      // eliminated right-hand side y for the backward pass.
-      double zc = (it == 0) ? 1.0 + 0.5 * hash_unit(0, 977 + t) : z[0];
-      double cur_d = al[0] - th;
-      double cur_u = (k > 1) ? be[0] : 0.0;
-      double cur_u2 = 0.0;
-      for (int i = 0; i < k - 1; ++i) {
-        const double sub = be[i];
-        const double nd = al[i + 1] - th;
-        const double nu = (i + 1 < k - 1) ? be[i + 1] : 0.0;
-        const double zn = (it == 0) ? 1.0 + 0.5 * hash_unit((uint64_t)(i + 1), 977 + t) : z[i + 1];
-        double di, u1, u2, y;
-        if (fabs(cur_d) >= fabs(sub)) {
-          di = (cur_d == 0.0) ? pert : cur_d;
-          const double mlt = sub / di;
-          u1 = cur_u;
-          u2 = cur_u2;
-          y = zc;
-          zc = zn - mlt * zc;
-          cur_d = nd - mlt * cur_u;
-          cur_u = nu - mlt * cur_u2;
-        } else {
-          const double mlt = cur_d / sub;
-          di = sub;
-          u1 = nd;
-          u2 = nu;
-          y = zn;
-          zc = zc - mlt * zn;
-          const double nd2 = cur_u - mlt * nd;
-          const double nu2 = cur_u2 - mlt * nu;
-          cur_d = nd2;
-          cur_u = nu2;
-        }
-        cur_u2 = 0.0;
-        wk[((int64_t)i * 4 + 0) * nr + t] = di;
-        wk[((int64_t)i * 4 + 1) * nr + t] = u1;
-        wk[((int64_t)i * 4 + 2) * nr + t] = u2;
-        wk[((int64_t)i * 4 + 3) * nr + t] = y;
-      }
-      double dl = (cur_d == 0.0) ? pert : cur_d;
-      if (fabs(dl) < pert) dl = (dl < 0 ? -pert : pert);
-      // backward substitution with a rolling window of two values
-      double z1 = zc / dl, z2 = 0.0;
-      double nn = z1 * z1;
-      z[k - 1] = z1;
-      for (int i = k - 2; i >= 0; --i) {
-        double di = wk[((int64_t)i * 4 + 0) * nr + t];
-        const double u1 = wk[((int64_t)i * 4 + 1) * nr + t];
-        const double u2 = wk[((int64_t)i * 4 + 2) * nr + t];
-        const double y = wk[((int64_t)i * 4 + 3) * nr + t];
-        if (fabs(di) < pert) di = (di < 0 ? -pert : pert);
-        const double zi = (y - u1 * z1 - u2 * z2) / di;
-        z2 = z1;
-        z1 = zi;
-        z[i] = zi;
-        nn = fma(zi, zi, nn);
-      }
-      const double inv = 1.0 / sqrt(nn);
-      for (int i = 0; i < k; ++i) z[i] *= inv;
-    }
-    __syncthreads();
-    // modified Gram-Schmidt inside clusters of close eigenvalues
-    for (int tt = 1; tt < nr; ++tt) {
-      bool any = false;
-      for (int ss = 0; ss < tt; ++ss) any |= fabs(theta[tt] - theta[ss]) <= cluster_gap;
-      if (!any) continue;
-      double* zt = S + (int64_t)tt * ldS;
-      for (int ss = 0; ss < tt; ++ss) {
-        if (fabs(theta[tt] - theta[ss]) > cluster_gap) continue;
-        const double* zs = S + (int64_t)ss * ldS;
-        double d = 0.0;
-        for (int i = t; i < k; i += 256) d = fma(zs[i], zt[i], d);
-        d = block_sum4(d, sh4);
-        for (int i = t; i < k; i += 256) zt[i] -= d * zs[i];
-        __syncthreads();
-      }
-      double nn = 0.0;
-      for (int i = t; i < k; i += 256) nn = fma(zt[i], zt[i], nn);
-      nn = block_sum4(nn, sh4);
-      const double inv = 1.0 / sqrt(nn);
-      for (int i = t; i < k; i += 256) zt[i] *= inv;
-      __syncthreads();
-    }
-  }
+  tridiag_top(al, be, k, nr, theta, S, ldS, wk);
   if (t < nr) {
     const double coupling = fabs(be[k - 1 < 0 ? 0 : k - 1]);
     theta_out[t] = theta[t];

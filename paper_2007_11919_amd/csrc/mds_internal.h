@@ -111,6 +111,11 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
 // ---- embed kernels (embed.hip) -----------------------------------------
 mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t n, int64_t ldx,
                         void* Y, int64_t ldy, hipStream_t st);
+// Divide-and-conquer MDS (dc.hip); arguments as mds_divide_conquer, already
+// validated.  Synchronous.
+mds_status dc_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int64_t c,
+                        int r, uint64_t seed, double* Y, int64_t ldy, double* lam_bar, int32_t* r_eff,
+                        int64_t* order_out, hipStream_t st);
 mds_status launch_embed_sqdist(const Model& m, int prec64, const void* A2, int dt, int64_t n,
                                int64_t lda, void* Y, int64_t ldy, hipStream_t st);
 // persistent serving launch over a device table of tiles

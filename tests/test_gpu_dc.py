@@ -1,0 +1,124 @@
+"""Divide-and-conquer MDS through the C ABI against the FP64 oracle (needs a
+GPU): the partition must match exactly, coordinates and eigenvalue
+estimates to FP64 tolerances."""
+
+import numpy as np
+import pytest
+
+from oracle import dc as odc
+from synth import errors
+from synth import generators as gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_Y = 1e-9     # worst column, max-abs error over the column's RMS
+TOL_LAM = 1e-12  # relative, eigenvalue estimates
+
+
+def mds():
+    import paper_2007_11919_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_and_compare(X, l, c, r, seed, parts=None, dtype=np.float64, ldx_pad=0, ldy_pad=0):
+    n, p = X.shape
+    Xs = X.astype(dtype)
+    if ldx_pad:
+        wide = np.zeros((n, p + ldx_pad), dtype=dtype)
+        wide[:, :p] = Xs
+        Xd = dev(wide)[:, :p]
+    else:
+        Xd = dev(Xs)
+    Y = None
+    if ldy_pad:
+        Y = torch.full((n, r + ldy_pad), 7.0, dtype=torch.float64, device="cuda")[:, :r]
+    Yg, lam_bar, r_eff, order = mds().divide_conquer(Xd, l, c, r, seed=seed, Y=Y, return_order=True)
+    res = odc.dc_mds(Xs.astype(np.float64), l, c, r, seed, parts=parts)
+    assert np.array_equal(order.cpu().numpy(), res.order), "partition differs"
+    assert r_eff == res.r_eff
+    Yg = Yg.cpu().numpy()
+    rows = np.arange(n) if parts is None else np.flatnonzero(~np.isnan(res.Y[:, 0]))
+    e = errors.column_errors(Yg[rows], res.Y[rows])
+    assert e["maxabs_rms"] <= TOL_Y, e
+    if r_eff < r:
+        assert np.all(Yg[:, r_eff:] == 0.0)
+    if res.lam_bar is not None:
+        ref = res.lam_bar
+        assert np.max(np.abs(lam_bar - ref)) <= TOL_LAM * np.max(np.abs(ref)), (lam_bar, ref)
+    if ldy_pad:
+        assert torch.all(Y.as_strided((n, ldy_pad), (r + ldy_pad, 1), r) == 7.0)
+    return Yg, res
+
+
+CASES = [
+    # (name, X builder, l, c, r)
+    ("c1 shape, feature Gram in LDS", lambda: gen.small_gaussian(5000, seed=11), 200, 10, 2),
+    ("paper design k=100 h=10", lambda: gen.paper_design(6000, 100, 10, seed=3), 400, 50, 10),
+    ("row Gram in LDS (p > l)", lambda: gen.image_mixture(1500, p=300, seed=4).astype(np.float64), 120, 20, 5),
+    ("row Gram in global memory", lambda: gen.image_mixture(1400, p=300, seed=5).astype(np.float64), 200, 20, 5),
+    ("feature Gram in global memory", lambda: gen.paper_design(3000, 150, 4, seed=6), 400, 20, 4),
+    ("one part (n <= l)", lambda: gen.small_gaussian(150, seed=7), 200, 10, 3),
+    ("last part one own row", lambda: gen.small_gaussian(1 + 30 + 7 * 90, seed=8), 120, 30, 3),
+    ("rank below r", lambda: gen.small_gaussian(2000, seed=9)[:, :3], 150, 12, 5),
+]
+
+
+@pytest.mark.parametrize("name,make,l,c,r", CASES, ids=[c[0] for c in CASES])
+def test_matches_oracle(name, make, l, c, r):
+    X = make()
+    run_and_compare(X, l, c, r, seed=5)
+
+
+def test_fp32_input_and_strides():
+    X = gen.paper_design(4000, 10, 2, seed=12)
+    run_and_compare(X, 400, 10, 2, seed=1, dtype=np.float32, ldx_pad=3, ldy_pad=2)
+
+
+def test_exact_recovery_of_low_rank_data():
+    X, _ = gen.low_rank(3000, 8, 3, seed=13)
+    Y, _ = run_and_compare(X, 300, 15, 3, seed=2)
+    sub = np.arange(0, 3000, 11)
+    dx = ((X[sub, None, :] - X[None, sub, :]) ** 2).sum(-1)
+    dy = ((Y[sub, None, :] - Y[None, sub, :]) ** 2).sum(-1)
+    assert np.max(np.abs(dx - dy)) <= 1e-9 * np.max(dx)
+
+
+def test_reproducible_bitwise():
+    X = dev(gen.paper_design(5000, 100, 10, seed=14).astype(np.float32))
+    a = mds().divide_conquer(X, 400, 50, 10, seed=3)[0].cpu().numpy()
+    b = mds().divide_conquer(X, 400, 50, 10, seed=3)[0].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_full_size_sampled_parts():
+    """Largest simulation scenario of Section 4.1 (n = 10^6, k = 100, h = 10)
+    with the divide-and-conquer settings l = 400, c = 5r: the whole
+    partition is compared, and the coordinates of four parts (the first,
+    the second, a middle one, the last) are recomputed by the oracle."""
+    n = 1_000_000
+    X = gen.paper_design(n, 100, 10, seed=15, dtype=np.float32)
+    P = odc.num_parts(n, 400, 50)
+    run_and_compare(X, 400, 50, 10, seed=6, parts={1, P // 2, P - 1}, dtype=np.float32)
+
+
+def test_error_codes():
+    m = mds()
+    X = dev(gen.small_gaussian(500, seed=16))
+    for l, c, r in [(100, 2, 2), (50, 50, 2), (600, 500, 2), (5000, 10, 2)]:
+        with pytest.raises(m.MDSError) as ei:
+            m.divide_conquer(X, l, c, r)
+        assert ei.value.status == 1, (l, c, r)
+    bad = gen.small_gaussian(500, seed=16)
+    bad[77, 3] = np.nan
+    with pytest.raises(m.MDSError) as ei:
+        m.divide_conquer(dev(bad), 100, 10, 2)
+    assert ei.value.status == 1
+    same = np.ones((500, 4))
+    with pytest.raises(m.MDSError) as ei:
+        m.divide_conquer(dev(same), 100, 10, 2)
+    assert ei.value.status == 4
