@@ -269,6 +269,75 @@ def sqdist_leg(mds, torch, model, Xd, Y32, iters):
             "rms_rel_vs_fp32_embed": err["rms_rel"]}
 
 
+DC = dict(n=1_000_000, k=100, h=10, l=400, c=50, r=10,
+          desc="divide-and-conquer MDS, 1,000,000 x 100 rows of the simulation design "
+               "(10 columns of variance 15, 90 of variance 1), l=400, c=5r=50, r=10; "
+               "FP32 input, FP64 arithmetic")
+
+
+def dc_flops(n, p, l, c, r):
+    """FP64 flops of divide-and-conquer MDS through the p x p Gram matrix:
+    per part of m rows, Gram 2 m p^2, Householder tridiagonalisation
+    4/3 p^3, back-transformation 4 p^2 r, coordinates 2 m p r."""
+    from oracle import dc as odc
+    P = odc.num_parts(n, l, c)
+    tot = 0.0
+    for j in range(P):
+        m = l if j < P - 1 else n - (P - 1) * (l - c)
+        tot += 2.0 * m * p * p + 4.0 / 3.0 * p ** 3 + 4.0 * p * p * r + 2.0 * m * p * r
+    return tot, P
+
+
+def dc_leg(mds, torch, iters, cpu):
+    """mds_divide_conquer at the largest simulation scenario of Section 4.1
+    with the paper's divide-and-conquer settings (l = 400, c = 5r)."""
+    from synth import generators as gen
+    from synth import errors
+    from oracle import dc as odc
+    d = DC
+    X = gen.paper_design(d["n"], d["k"], d["h"], seed=15, dtype=np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    st = torch.cuda.current_stream()
+    Y, lam_bar, r_eff = mds.divide_conquer(Xd, d["l"], d["c"], d["r"], seed=6)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    t = time.perf_counter()
+    for _ in range(iters):
+        mds.divide_conquer(Xd, d["l"], d["c"], d["r"], seed=6, Y=Y)
+    wall = (time.perf_counter() - t) / iters
+    e1.record(st)
+    torch.cuda.synchronize()
+    dev_s = e0.elapsed_time(e1) / 1e3 / iters
+    flops, P = dc_flops(d["n"], d["k"], d["l"], d["c"], d["r"])
+    out = {"config": d["desc"], "parts": P, "ms": wall * 1e3, "ms_stream": dev_s * 1e3,
+           "points_per_s": d["n"] / wall, "lam_bar": [float(v) for v in lam_bar], "r_eff": r_eff,
+           "fp64": {"algorithmic_gflop": flops / 1e9, "achieved_tflops": flops / wall / 1e12,
+                    "peak_tflops": 78.6, "frac": flops / wall / 78.6e12}}
+    Yn = Y.cpu().numpy()
+    parts = {1, P // 2, P - 1}
+    X64 = X.astype(np.float64)
+    t = time.perf_counter()
+    ref = odc.dc_mds(X64, d["l"], d["c"], d["r"], 6, parts=parts)
+    t_orc = time.perf_counter() - t
+    rows = np.flatnonzero(~np.isnan(ref.Y[:, 0]))
+    e = errors.column_errors(Yn[rows], ref.Y[rows])
+    out["err_vs_oracle_parts"] = {"parts": sorted(parts | {0}),
+                                  **{k: e[k] for k in ("rms_rel", "maxabs_rms", "frob_rel")}}
+    if cpu:
+        # partition plus 4 parts of classical MDS and alignment on the host,
+        # scaled to all parts
+        per_part = t_orc / 4.0
+        whole = per_part * P
+        out["cpu_baseline"] = {"value": d["n"] / whole, "unit": "points/s",
+                               "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                               "sample": f"oracle on 4 of {P} parts ({t_orc:.2f} s, partition "
+                                         f"of all rows included), scaled to all parts"}
+    del Xd
+    return out
+
+
 def cpu_baseline(name, X, w, sample_rows, Ys_gpu):
     """The FP64 oracle, as it stands, on the host cores: full fit plus the
     embed of a bounded sample of rows, scaled to rows per second of a whole
@@ -316,6 +385,9 @@ def main():
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--only-fit", action="store_true", help="run --iters fits only (profiling)")
     ap.add_argument("--copy-calib", type=int, default=0)
+    ap.add_argument("--no-dc", action="store_true")
+    ap.add_argument("--dc-iters", type=int, default=5)
+    ap.add_argument("--only-dc", action="store_true", help="run --iters divide-and-conquer calls only")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -337,6 +409,16 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes": n * 4, "launches": 5}))
+        return
+
+    if args.only_dc:
+        from synth import generators as gen
+        X = gen.paper_design(DC["n"], DC["k"], DC["h"], seed=15, dtype=np.float32)
+        Xd = torch.from_numpy(X).to(dev)
+        for _ in range(args.iters):
+            mds.divide_conquer(Xd, DC["l"], DC["c"], DC["r"], seed=6)
+        torch.cuda.synchronize()
+        print(json.dumps({"only_dc": args.iters}))
         return
 
     w = WORKLOADS[args.workload]
@@ -429,6 +511,9 @@ def main():
     if args.workload == "wide" and not args.no_sqdist:
         log("embedding from squared dissimilarities")
         out["embed_from_sqdist"] = sqdist_leg(mds, torch, model, Xd, Y32, args.embed_iters)
+    if args.workload == "wide" and not args.no_dc:
+        log("divide-and-conquer MDS")
+        out["divide_conquer"] = dc_leg(mds, torch, args.dc_iters, not args.no_cpu_baseline)
     if not args.no_serve:
         log("serving runs")
         budget = 8 << 30

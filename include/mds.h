@@ -176,7 +176,7 @@ mds_status mds_embed_from_sqdist(const mds_model* m, const void* A2, int32_t dt,
  * whose rows all coincide, or connecting rows that do not fix the rotation:
  * smallest singular value of the cross-product matrix <= 1e-9 of the
  * largest), OOM, HIP. */
-#define MDS_DC_MAX_L 4096
+#define MDS_DC_MAX_L 2048
 mds_status mds_divide_conquer(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx,
                               int64_t l, int64_t c, int32_t r, uint64_t seed, double* Y,
                               int64_t ldy, double* lam_bar, int32_t* r_eff, int64_t* order_out,

@@ -277,7 +277,7 @@ mds_status mds_divide_conquer(const void* X, int32_t dt, int64_t n, int64_t p, i
   if (ldy < r) return set_error(MDS_ERR_INVALID_ARG, "ldy < r");
   if (c < (int64_t)r + 1) return set_error(MDS_ERR_INVALID_ARG, "need c >= r + 1");
   if (l <= c) return set_error(MDS_ERR_INVALID_ARG, "need l > c");
-  if (l > MDS_DC_MAX_L) return set_error(MDS_ERR_INVALID_ARG, "l too large (max 4096)");
+  if (l > MDS_DC_MAX_L) return set_error(MDS_ERR_INVALID_ARG, "l too large (max 2048)");
   if (n <= c) return set_error(MDS_ERR_INVALID_ARG, "need n > c");
   if (n > ((int64_t)1 << 40)) return set_error(MDS_ERR_INVALID_ARG, "n too large");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -209,6 +209,52 @@ __global__ __launch_bounds__(256) void k_dc_gram_rows(const TX* __restrict__ X, 
 }
 
 // ------------------------------------------------------- dense eigensolver
+constexpr int DC_NT = 512;         // threads of the per-part eigensolver block
+constexpr int DC_NW = DC_NT / 64;  // its waves
+
+// A22 -= v w' + w v' with w = p - K v over the rows i = wv (mod DC_NW),
+// lanes along the row, four rows loaded before any is stored.  Both
+// products are rounded before the sum, so A22 stays exactly symmetric.
+// Returns this lane's part of the squared norm of row 0 beyond its first two
+// entries (the next column below its subdiagonal).
+__device__ __forceinline__ double dc_rank2(double* __restrict__ A22, int lda,
+                                           const double* __restrict__ vv,
+                                           const double* __restrict__ pw, double K, int n2,
+                                           int wv, int lane) {
+  double ps = 0.0;
+  for (int jc0 = 0; jc0 < n2; jc0 += 64) {
+    const int jj = jc0 + lane;
+    if (jj >= n2) continue;
+    const double vj = vv[jj];
+    const double wj = fma(-K, vj, pw[jj]);
+    for (int i0 = wv; i0 < n2; i0 += 4 * DC_NW) {
+      double vi[4], wi[4], av[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * DC_NW;
+        vi[u] = 0.0;
+        wi[u] = 0.0;
+        av[u] = 0.0;
+        if (i < n2) {
+          vi[u] = vv[i];
+          wi[u] = fma(-K, vi[u], pw[i]);
+          av[u] = A22[(int64_t)i * lda + jj];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * DC_NW;
+        if (i < n2) {
+          const double nv = av[u] - (__dmul_rn(vi[u], wj) + __dmul_rn(wi[u], vj));
+          A22[(int64_t)i * lda + jj] = nv;
+          if (i == 0 && jj >= 2) ps = fma(nv, nv, ps);
+        }
+      }
+    }
+  }
+  return ps;
+}
+
 // One block per part.  The symmetric matrix (dd x dd, full storage) is
 // reduced to tridiagonal form by Householder reflections H_k = I - tau_k v v'
 // (LAPACK's unblocked lower reduction); v_k is kept in row k, which later
@@ -221,14 +267,16 @@ __global__ __launch_bounds__(256) void k_dc_gram_rows(const TX* __restrict__ X, 
 // Xs[j][i][t] = v_t[i] sqrt(lam_t) (zero where lam_t <= 0).  status[j] = 1
 // when lam_1 <= 0 (all rows of the part coincide).
 template <bool IN_LDS>
-__global__ __launch_bounds__(256) void k_dc_eigen(double* __restrict__ G, int d, DcShape s,
+__global__ __launch_bounds__(DC_NT) void k_dc_eigen(double* __restrict__ G, int d, DcShape s,
                                                   int rows_gram, int64_t j0, int nr,
                                                   double* __restrict__ zg, double* __restrict__ wkg,
+                                                  double* __restrict__ partg,
                                                   double* __restrict__ lam, double* __restrict__ U,
                                                   double* __restrict__ Xs, int* __restrict__ status) {
   extern __shared__ double dsm[];
-  __shared__ double sh4[4];
+  __shared__ double shw[DC_NW];
   __shared__ double theta[MDS_MAX_R];
+  __shared__ double sig_next;
   const int t = threadIdx.x;
   const int64_t jc = blockIdx.x, j = j0 + jc;
   const int dd = rows_gram ? (int)dc_part_size(j, s) : d;
@@ -244,9 +292,9 @@ __global__ __launch_bounds__(256) void k_dc_eigen(double* __restrict__ G, int d,
     be = al + dd;
     tau = be + dd;
     pw = tau + dd;
-    Z = pw + dd;
+    Z = pw + (2 + DC_NW) * dd;  // pw, vv, one partial row per wave
     wk = Z + (int64_t)nr * dd;
-    for (int64_t e = t; e < (int64_t)dd * dd; e += 256) A[e] = Gp[(e / dd) * d + (e % dd)];
+    for (int64_t e = t; e < (int64_t)dd * dd; e += DC_NT) A[e] = Gp[(e / dd) * d + (e % dd)];
   } else {
     lda = d;
     ldz = d;
@@ -260,12 +308,24 @@ __global__ __launch_bounds__(256) void k_dc_eigen(double* __restrict__ G, int d,
   }
   __syncthreads();
 
+  // Reduction to tridiagonal form.  Per step: v from the column below the
+  // diagonal; p = tau A22 v (wave w sums the columns jj = w mod DC_NW, lanes
+  // run down the rows, the wave partials are added in order); K = tau p'v / 2;
+  // A22 -= v w' + w v' with w = p - K v.  The next column's squared norm is
+  // accumulated while its row is updated.
+  double* vv = pw + dd;                                      // v of the current step
+  double* part = IN_LDS ? vv + dd : partg + jc * DC_NW * (int64_t)d;  // DC_NW x dd partials
+  const int wv = t >> 6, lane = t & 63;
+  double sigma = 0.0;
+  if (dd >= 3) {
+    double ps = 0.0;
+    for (int i = 2 + t; i < dd; i += DC_NT) ps = fma(A[i], A[i], ps);
+    sigma = block_sum_n<DC_NT>(ps, shw);
+  }
   for (int k = 0; k + 2 < dd; ++k) {
     const int n2 = dd - k - 1;
     double* rowk = A + (int64_t)k * lda + (k + 1);  // column k below the diagonal, by symmetry
-    double part = 0.0;
-    for (int i = 1 + t; i < n2; i += 256) part = fma(rowk[i], rowk[i], part);
-    const double sigma = block_sum4(part, sh4);
+    double* A22 = rowk + lda;                       // A[k+1][k+1]
     const double x0 = rowk[0];
     if (t == 0) al[k] = A[(int64_t)k * lda + k];
     if (sigma == 0.0) {  // already tridiagonal in this column: H_k = I
@@ -273,39 +333,53 @@ __global__ __launch_bounds__(256) void k_dc_eigen(double* __restrict__ G, int d,
         tau[k] = 0.0;
         be[k] = x0;
       }
+      double ps = 0.0;
+      for (int i = 2 + t; i < n2; i += DC_NT) ps = fma(A22[i], A22[i], ps);
+      sigma = block_sum_n<DC_NT>(ps, shw);
       continue;
     }
     const double beta = -copysign(sqrt(x0 * x0 + sigma), x0);
     const double tk = (beta - x0) / beta;
     const double scale = 1.0 / (x0 - beta);
-    __syncthreads();  // x0 is read by every thread before row k is rewritten
-    for (int i = 1 + t; i < n2; i += 256) rowk[i] *= scale;
+    for (int i = t; i < n2; i += DC_NT) vv[i] = (i == 0) ? 1.0 : rowk[i] * scale;
     if (t == 0) {
-      rowk[0] = 1.0;
       tau[k] = tk;
       be[k] = beta;
     }
     __syncthreads();
-    // p = tau A22 v, reading columns of the symmetric trailing block
-    double* A22 = A + (int64_t)(k + 1) * lda + (k + 1);
-    for (int i = t; i < n2; i += 256) {
-      double acc = 0.0;
-      for (int jj = 0; jj < n2; ++jj) acc = fma(A22[(int64_t)jj * lda + i], rowk[jj], acc);
-      pw[i] = tk * acc;
+    for (int i0 = 0; i0 < n2; i0 += 64) {
+      const int i = i0 + lane;
+      if (i < n2) {
+        double a0 = 0.0, a1 = 0.0;
+        int jj = wv;
+        for (; jj + DC_NW < n2; jj += 2 * DC_NW) {
+          a0 = fma(A22[(int64_t)jj * lda + i], vv[jj], a0);
+          a1 = fma(A22[(int64_t)(jj + DC_NW) * lda + i], vv[jj + DC_NW], a1);
+        }
+        if (jj < n2) a0 = fma(A22[(int64_t)jj * lda + i], vv[jj], a0);
+        part[wv * dd + i] = a0 + a1;
+      }
     }
     __syncthreads();
     double pv = 0.0;
-    for (int i = t; i < n2; i += 256) pv = fma(pw[i], rowk[i], pv);
-    const double K = 0.5 * tk * block_sum4(pv, sh4);
-    for (int i = t; i < n2; i += 256) pw[i] = pw[i] - K * rowk[i];  // w
-    __syncthreads();
-    // A22 -= v w' + w v'; both products are rounded before the sum, so the
-    // update keeps A22 exactly symmetric
-    for (int64_t e = t; e < (int64_t)n2 * n2; e += 256) {
-      const int i = (int)(e / n2), jj = (int)(e % n2);
-      A22[(int64_t)i * lda + jj] -= __dmul_rn(rowk[i], pw[jj]) + __dmul_rn(pw[i], rowk[jj]);
+    for (int i = t; i < n2; i += DC_NT) {
+      double sp = part[i];
+#pragma unroll
+      for (int w = 1; w < DC_NW; ++w) sp += part[w * dd + i];
+      const double pi = tk * sp;
+      pw[i] = pi;
+      pv = fma(pi, vv[i], pv);
+    }
+    const double K = 0.5 * tk * block_sum_n<DC_NT>(pv, shw);
+    double ps = dc_rank2(A22, lda, vv, pw, K, n2, wv, lane);
+    for (int i = t; i < n2; i += DC_NT) rowk[i] = vv[i];  // v_k, kept for the back-transformation
+    if (wv == 0) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) ps += __shfl_xor(ps, off, 64);
+      if (lane == 0) sig_next = ps;
     }
     __syncthreads();
+    sigma = sig_next;
   }
   if (t == 0) {
     if (dd >= 2) {
@@ -317,17 +391,16 @@ __global__ __launch_bounds__(256) void k_dc_eigen(double* __restrict__ G, int d,
   }
   __syncthreads();
 
-  tridiag_top(al, be, dd, nrr, theta, Z, ldz, wk);
+  tridiag_top<DC_NT>(al, be, dd, nrr, theta, Z, ldz, wk, pw);  // pw is free now
   __syncthreads();
 
-  // back-transformation; wave w owns vectors w, w+4, ...
-  const int wv = t >> 6, lane = t & 63;
+  // back-transformation; wave w owns vectors w, w + DC_NW, ...
   for (int k = dd - 3; k >= 0; --k) {
     const double tk = tau[k];
     if (tk == 0.0) continue;
     const double* v = A + (int64_t)k * lda + (k + 1);
     const int n2 = dd - k - 1;
-    for (int tt = wv; tt < nrr; tt += 4) {
+    for (int tt = wv; tt < nrr; tt += DC_NW) {
       double* z = Z + (int64_t)tt * ldz + (k + 1);
       double dot = 0.0;
       for (int i = lane; i < n2; i += 64) dot = fma(v[i], z[i], dot);
@@ -340,15 +413,15 @@ __global__ __launch_bounds__(256) void k_dc_eigen(double* __restrict__ G, int d,
   }
   __syncthreads();
 
-  for (int tt = t; tt < s.r; tt += 256) lam[j * s.r + tt] = tt < nrr ? theta[tt] : 0.0;
+  for (int tt = t; tt < s.r; tt += DC_NT) lam[j * s.r + tt] = tt < nrr ? theta[tt] : 0.0;
   if (t == 0) status[j] = (nrr > 0 && theta[0] > 0.0) ? 0 : 1;
   if (!rows_gram) {
-    for (int64_t e = t; e < (int64_t)dd * s.r; e += 256) {
+    for (int64_t e = t; e < (int64_t)dd * s.r; e += DC_NT) {
       const int i = (int)(e / s.r), tt = (int)(e % s.r);
       U[(j * d + i) * s.r + tt] = tt < nrr ? Z[(int64_t)tt * ldz + i] : 0.0;
     }
   } else {
-    for (int64_t e = t; e < (int64_t)dd * s.r; e += 256) {
+    for (int64_t e = t; e < (int64_t)dd * s.r; e += DC_NT) {
       const int i = (int)(e / s.r), tt = (int)(e % s.r);
       double v = 0.0;
       if (tt < nrr && theta[tt] > 0.0) v = Z[(int64_t)tt * ldz + i] * sqrt(theta[tt]);
@@ -410,9 +483,45 @@ __global__ __launch_bounds__(256) void k_dc_coords(const TX* __restrict__ X, int
   }
 }
 
+// ----------------------------------------------------- signs of part 0
+// For each live column of X_0: +1 or -1 making its largest-|.| entry
+// positive (first row in part order on ties).  One block; wave w scans the
+// columns t = w (mod 4), lanes take rows i = lane (mod 64), and the lane
+// maxima are merged by a butterfly that keeps the larger magnitude and, on
+// equal magnitudes, the smaller row.
+__global__ __launch_bounds__(256) void k_dc_signs(const double* __restrict__ Xs, DcShape s, int r0,
+                                                  double* __restrict__ sgn) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t m0 = dc_part_size(0, s);
+  for (int t = wv; t < r0; t += 4) {
+    double best = -1.0, val = 0.0;
+    int64_t at = INT64_MAX;
+    for (int64_t i = lane; i < m0; i += 64) {
+      const double v = Xs[i * s.r + t];
+      if (fabs(v) > best) {
+        best = fabs(v);
+        val = v;
+        at = i;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const double ov = __shfl_xor(val, off, 64);
+      const int64_t oa = __shfl_xor(at, off, 64);
+      if (ob > best || (ob == best && oa < at)) {
+        best = ob;
+        val = ov;
+        at = oa;
+      }
+    }
+    if (lane == 0) sgn[t] = val < 0.0 ? -1.0 : 1.0;
+  }
+}
+
 // ------------------------------------------------------------- alignment
-// One block per part.  Part 0: the sign of each live column is fixed
-// (largest-|.| entry positive, first row on ties) and its rows are written.
+// One block per part.  Part 0: its rows are written with the column signs
+// from k_dc_signs.
 // Part j >= 1: Procrustes fit on the c connecting rows over the r0 live
 // columns: C = (B - 1b')'(A - 1a') (B: part j, A: part 0), C = U S W' by
 // one-sided Jacobi (Hestenes) in one wave, T = U W', t = a - T' b; own rows
@@ -420,7 +529,8 @@ __global__ __launch_bounds__(256) void k_dc_coords(const TX* __restrict__ X, int
 // smallest singular value of C is <= 1e-9 of the largest.
 __global__ __launch_bounds__(256) void k_dc_align(const double* __restrict__ Xs,
                                                   const int64_t* __restrict__ order, DcShape s,
-                                                  int r0, double* __restrict__ Y, int64_t ldy,
+                                                  int r0, const double* __restrict__ sgn_g,
+                                                  double* __restrict__ Y, int64_t ldy,
                                                   int* __restrict__ status) {
   extern __shared__ double dyn[];
   __shared__ double sgn[MDS_MAX_R];
@@ -440,17 +550,7 @@ __global__ __launch_bounds__(256) void k_dc_align(const double* __restrict__ Xs,
   const double* X0 = Xs;
   const double* Xj = Xs + j * s.m_max * r;
   const int64_t m0 = dc_part_size(0, s);
-  if (t < r0) {
-    double best = -1.0, val = 0.0;
-    for (int64_t i = 0; i < m0; ++i) {
-      const double v = X0[i * r + t];
-      if (fabs(v) > best) {
-        best = fabs(v);
-        val = v;
-      }
-    }
-    sgn[t] = val < 0.0 ? -1.0 : 1.0;
-  }
+  if (t < r0) sgn[t] = sgn_g[t];
   __syncthreads();
   if (j == 0) {
     for (int64_t e = t; e < m0 * r; e += 256) {
@@ -589,8 +689,8 @@ constexpr size_t kDcLdsMax = 150 * 1024;
 constexpr size_t kDcGramBudget = (size_t)1 << 30;
 
 size_t eigen_lds_bytes(int d, int nr) {
-  // A, four vectors, Z and the inverse-iteration work
-  return sizeof(double) * ((size_t)d * d + 4 * (size_t)d + (size_t)nr * d + 4 * (size_t)d * nr);
+  // A, five vectors, one partial row per wave, Z and the inverse-iteration work
+  return sizeof(double) * ((size_t)d * d + (5 + DC_NW) * (size_t)d + (size_t)nr * d + 4 * (size_t)d * nr);
 }
 
 template <typename TX>
@@ -605,7 +705,7 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
   const int64_t chunk =
       std::max<int64_t>(1, std::min<int64_t>(np, (int64_t)(kDcGramBudget / (sizeof(double) * (size_t)d * d))));
 
-  DevMem keys_in, keys_out, vals, order_buf, tmp, mean, lam, status, U, Xs, G, zg, wkg, bad;
+  DevMem keys_in, keys_out, vals, order_buf, tmp, mean, lam, status, U, Xs, G, zg, wkg, partg, bad, sgn;
   auto alloc = [&](DevMem& b, size_t bytes) -> hipError_t {
     b.st = st;
     return hipMallocAsync(&b.p, std::max<size_t>(bytes, 256), st);
@@ -627,8 +727,10 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
   if (!in_lds) {
     DC_HIP(alloc(zg, sizeof(double) * chunk * nr * d));
     DC_HIP(alloc(wkg, sizeof(double) * chunk * 4 * d * nr));
+    DC_HIP(alloc(partg, sizeof(double) * chunk * DC_NW * d));
   }
   DC_HIP(alloc(bad, sizeof(int)));
+  DC_HIP(alloc(sgn, sizeof(double) * MDS_MAX_R));
   DC_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
 
   // partition: keys, then a stable radix sort of (key, row)
@@ -668,13 +770,14 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
       k_dc_gram_feat<TX><<<ggrid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), j0, G.get<double>());
     DC_LAUNCH("part Gram matrices");
     if (in_lds)
-      k_dc_eigen<true><<<(unsigned)cnt, 256, eigen_lds_bytes(d, nr), st>>>(
-          G.get<double>(), d, s, rows_gram ? 1 : 0, j0, nr, nullptr, nullptr, lam.get<double>(),
-          U.get<double>(), Xs.get<double>(), status.get<int>());
-    else
-      k_dc_eigen<false><<<(unsigned)cnt, 256, sizeof(double) * 4 * (size_t)d, st>>>(
-          G.get<double>(), d, s, rows_gram ? 1 : 0, j0, nr, zg.get<double>(), wkg.get<double>(),
+      k_dc_eigen<true><<<(unsigned)cnt, DC_NT, eigen_lds_bytes(d, nr), st>>>(
+          G.get<double>(), d, s, rows_gram ? 1 : 0, j0, nr, nullptr, nullptr, nullptr,
           lam.get<double>(), U.get<double>(), Xs.get<double>(), status.get<int>());
+    else
+      k_dc_eigen<false><<<(unsigned)cnt, DC_NT, sizeof(double) * 5 * (size_t)d, st>>>(
+          G.get<double>(), d, s, rows_gram ? 1 : 0, j0, nr, zg.get<double>(), wkg.get<double>(),
+          partg.get<double>(), lam.get<double>(), U.get<double>(), Xs.get<double>(),
+          status.get<int>());
     DC_LAUNCH("part eigensolver");
   }
   if (!rows_gram) {
@@ -696,9 +799,11 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
   int r0 = 0;
   for (int t = 0; t < r; ++t)
     if (hlam[t] > MDS_TAU * hlam[0]) ++r0;
+  k_dc_signs<<<1, 256, 0, st>>>(Xs.get<double>(), s, r0, sgn.get<double>());
+  DC_LAUNCH("signs of the first part");
   const size_t align_lds = sizeof(double) * 3 * (size_t)r0 * (r0 + 1);
-  k_dc_align<<<(unsigned)np, 256, align_lds, st>>>(Xs.get<double>(), order, s, r0, Y, ldy,
-                                                   status.get<int>());
+  k_dc_align<<<(unsigned)np, 256, align_lds, st>>>(Xs.get<double>(), order, s, r0, sgn.get<double>(),
+                                                   Y, ldy, status.get<int>());
   DC_LAUNCH("alignment");
   DC_HIP(hipMemcpyAsync(hstat.data(), status.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
   DC_HIP(hipStreamSynchronize(st));

@@ -320,8 +320,9 @@ __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alph
     be[i] = beta[i];
   }
   __syncthreads();
-  double* wk = work_in_lds ? (sm + 2 * k) : gwork;  // [4 arrays][k][nr]
-  tridiag_top(al, be, k, nr, theta, S, ldS, wk);
+  double* be2 = sm + 2 * k;
+  double* wk = work_in_lds ? (sm + 3 * k) : gwork;  // [4 arrays][k][nr]
+  tridiag_top<256>(al, be, k, nr, theta, S, ldS, wk, be2);
   if (t < nr) {
     const double coupling = fabs(be[k - 1 < 0 ? 0 : k - 1]);
     theta_out[t] = theta[t];
@@ -520,7 +521,7 @@ hipError_t launch_tridiag(const double* alpha, const double* beta, const int* ct
     attr = true;
   }
   const int nr = std::min(r, k_host);
-  const size_t base = sizeof(double) * 2 * (size_t)k_host;
+  const size_t base = sizeof(double) * 3 * (size_t)k_host;
   const size_t work = sizeof(double) * 4 * (size_t)k_host * nr;
   const int in_lds = (base + work <= kTriLdsMax) ? 1 : 0;
   k_tridiag<<<1, 256, base + (in_lds ? work : 0), st>>>(alpha, beta, ctrl, k_host, r, theta, bound, S,

@@ -1,7 +1,8 @@
 // Device helpers shared by the eigensolvers of the fit and of
-// divide-and-conquer MDS: a hash for start vectors, a fixed-order block
-// sum, and the symmetric tridiagonal solver that returns the largest
-// eigenpairs.  Every function here is called by a whole 256-thread block.
+// divide-and-conquer MDS: a hash for start vectors, fixed-order block sums,
+// and the symmetric tridiagonal solver that returns the largest eigenpairs.
+// The block functions are called by every thread of a block of NT threads
+// (a multiple of 64).
 #ifndef MDS_TRIDIAG_DEV_H
 #define MDS_TRIDIAG_DEV_H
 
@@ -37,48 +38,143 @@ __device__ inline double block_sum4(double v, double* sh4) {
   return r;
 }
 
-__device__ inline int sturm_count(const double* alpha, const double* beta, int k, double x,
+// the same for a block of NT threads: NT / 64 wave partials in order
+template <int NT>
+__device__ inline double block_sum_n(double v, double* shw) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) shw[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = shw[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) r += shw[w];
+  __syncthreads();
+  return r;
+}
+
+// 1/d from the hardware reciprocal refined by two Newton steps (each
+// squares the relative error), good to about an ulp; d must be a normal
+// number.  Cheaper than a correctly rounded division, which the Sturm
+// recurrence does not need: an O(eps) relative change of each pivot is a
+// perturbation of T of the same order.
+__device__ inline double rcp_refined(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  return r;
+}
+
+__device__ inline int sturm_count(const double* alpha, const double* beta2, int k, double x,
                                   double pivmin) {
-  // number of eigenvalues of T below x
+  // number of eigenvalues of T below x (beta2 holds the squared
+  // off-diagonal); pivots smaller than pivmin are replaced by -pivmin
   int cnt = 0;
   double d = alpha[0] - x;
   if (fabs(d) < pivmin) d = -pivmin;
   if (d < 0) ++cnt;
   for (int i = 1; i < k; ++i) {
-    const double b = beta[i - 1];
-    d = (alpha[i] - x) - b * b / d;
+    d = (alpha[i] - x) - beta2[i - 1] * rcp_refined(d);
     if (fabs(d) < pivmin) d = -pivmin;
     if (d < 0) ++cnt;
   }
   return cnt;
 }
 
+// One sweep of inverse iteration for the vector z (length k, replaced by
+// the normalised solution of (T - th I) x = z): LU factorisation with
+// partial pivoting, applied to the right-hand side on the fly, then the
+// backward substitution.  U is kept as (1/pivot, u1, u2) with the
+// eliminated right-hand side y in wk[i * 4 * nr + {0,1,2,3} * nr] (the
+// caller's column t).  Pivots smaller than pert in magnitude are replaced by
+// +-pert.  Thread-private: no barrier, no other thread's data.
+__device__ __forceinline__ void inverse_sweep(const double* __restrict__ al,
+                                              const double* __restrict__ be, int k, double th,
+                                              double pert, double* __restrict__ z,
+                                              double* __restrict__ wk, int nr) {
+  double zc = z[0];
+  double cur_d = al[0] - th;
+  double cur_u = (k > 1) ? be[0] : 0.0;
+  double cur_u2 = 0.0;
+  for (int i = 0; i < k - 1; ++i) {
+    const double sub = be[i];
+    const double nd = al[i + 1] - th;
+    const double nu = (i + 1 < k - 1) ? be[i + 1] : 0.0;
+    const double zn = z[i + 1];
+    double di, u1, u2, y;
+    if (fabs(cur_d) >= fabs(sub)) {
+      di = (fabs(cur_d) < pert) ? (cur_d < 0 ? -pert : pert) : cur_d;
+      const double mlt = sub * rcp_refined(di);
+      u1 = cur_u;
+      u2 = cur_u2;
+      y = zc;
+      zc = zn - mlt * zc;
+      cur_d = nd - mlt * cur_u;
+      cur_u = nu - mlt * cur_u2;
+    } else {
+      const double mlt = cur_d / sub;  // |sub| > |cur_d|; sub may be tiny
+      di = sub;
+      u1 = nd;
+      u2 = nu;
+      y = zn;
+      zc = zc - mlt * zn;
+      const double nd2 = cur_u - mlt * nd;
+      const double nu2 = cur_u2 - mlt * nu;
+      cur_d = nd2;
+      cur_u = nu2;
+    }
+    cur_u2 = 0.0;
+    double* w = wk + (int64_t)i * 4 * nr;
+    w[0] = rcp_refined((fabs(di) < pert) ? (di < 0 ? -pert : pert) : di);
+    w[nr] = u1;
+    w[2 * nr] = u2;
+    w[3 * nr] = y;
+  }
+  double dl = (fabs(cur_d) < pert) ? (cur_d < 0 ? -pert : pert) : cur_d;
+  // backward substitution with a rolling window of two values
+  double z1 = zc * rcp_refined(dl), z2 = 0.0;
+  double nn = z1 * z1;
+  z[k - 1] = z1;
+  for (int i = k - 2; i >= 0; --i) {
+    const double* w = wk + (int64_t)i * 4 * nr;
+    const double zi = (w[3 * nr] - w[nr] * z1 - w[2 * nr] * z2) * w[0];
+    z2 = z1;
+    z1 = zi;
+    z[i] = zi;
+    nn = fma(zi, zi, nn);
+  }
+  const double inv = 1.0 / sqrt(nn);
+  for (int i = 0; i < k; ++i) z[i] *= inv;
+}
+
 // The nr largest eigenpairs of the k x k symmetric tridiagonal T with
 // diagonal al[0..k) and off-diagonal be[0..k-1) (both readable by every
 // thread).  Eigenvalues by bisection on Sturm counts, multisected over the
-// 256 threads; eigenvectors by inverse iteration with partial pivoting,
+// NT threads; eigenvectors by inverse iteration with partial pivoting,
 // orthogonalised (modified Gram-Schmidt) within clusters of close
 // eigenvalues.  Output: theta[t] (shared, nr entries, descending) and the
-// unit vector of pair t at Z + t * ldz.  wk holds 4 * k * nr doubles.
+// unit vector of pair t at Z + t * ldz.  wk holds 4 * k * nr doubles and
+// be2 k doubles of scratch (both visible to the whole block).
+template <int NT>
 __device__ void tridiag_top(const double* al, const double* be, int k, int nr, double* theta,
-                            double* Z, int ldz, double* wk) {
-  __shared__ double sh[256];
-  __shared__ double sh4[4];
+                            double* Z, int ldz, double* wk, double* be2) {
+  __shared__ double sh[NT];
+  __shared__ double shw[NT / 64];
   __shared__ double ga[MDS_MAX_R], gb[MDS_MAX_R];
-  __shared__ int flag[256];
+  __shared__ int flag[NT];
   const int t = threadIdx.x;
   // Gershgorin interval and scale
   double lo = DBL_MAX, hi = -DBL_MAX, bmax = 0.0;
-  for (int i = t; i < k; i += 256) {
+  for (int i = t; i < k; i += NT) {
     const double bl = (i > 0) ? fabs(be[i - 1]) : 0.0;
     const double br = (i < k - 1) ? fabs(be[i]) : 0.0;
     lo = fmin(lo, al[i] - bl - br);
     hi = fmax(hi, al[i] + bl + br);
     bmax = fmax(bmax, br);
+    be2[i] = (i < k - 1) ? be[i] * be[i] : 0.0;
   }
   sh[t] = lo;
   __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+  for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
     if (t < s2) sh[t] = fmin(sh[t], sh[t + s2]);
     __syncthreads();
   }
@@ -86,7 +182,7 @@ __device__ void tridiag_top(const double* al, const double* be, int k, int nr, d
   __syncthreads();
   sh[t] = hi;
   __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+  for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
     if (t < s2) sh[t] = fmax(sh[t], sh[t + s2]);
     __syncthreads();
   }
@@ -94,7 +190,7 @@ __device__ void tridiag_top(const double* al, const double* be, int k, int nr, d
   __syncthreads();
   sh[t] = bmax;
   __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+  for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
     if (t < s2) sh[t] = fmax(sh[t], sh[t + s2]);
     __syncthreads();
   }
@@ -107,8 +203,7 @@ __device__ void tridiag_top(const double* al, const double* be, int k, int nr, d
   hi += 2.0 * eps * tnorm + pivmin;
 
   // All wanted eigenvalues at once: a group of G threads multisects each.
-  int G = 256;
-  while (G > 1 && G * nr > 256) G >>= 1;
+  const int G = (nr > 0) ? NT / nr : NT;
   const int grp = t / G, gl = t % G;
   const bool active = grp < nr;
   if (t < nr) {
@@ -124,19 +219,23 @@ __device__ void tridiag_top(const double* al, const double* be, int k, int nr, d
       more = (b - a > 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin) ? 1 : 0;
       if (more) {
         const double x = a + (b - a) * (double)(gl + 1) / (double)(G + 1);
-        flag[t] = sturm_count(al, be, k, x, pivmin) >= m + 1;
+        flag[t] = sturm_count(al, be2, k, x, pivmin) >= m + 1;
       }
     }
     if (!__syncthreads_or(more)) break;
     if (active && gl == 0) {
       const double a = ga[grp], b = gb[grp];
       if (b - a > 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin) {
-        int first = G;
-        for (int q = 0; q < G; ++q)
-          if (flag[grp * G + q]) {
-            first = q;
-            break;
-          }
+        // a transition false -> true of the flags (a at q = -1 counts as
+        // false, b at q = G as true); binary search keeps that invariant
+        int qlo = -1, first = G;
+        while (first - qlo > 1) {
+          const int mid = (qlo + first) >> 1;
+          if (flag[grp * G + mid])
+            first = mid;
+          else
+            qlo = mid;
+        }
         const double xa = (first == 0) ? a : a + (b - a) * (double)first / (double)(G + 1);
         const double xb = (first == G) ? b : a + (b - a) * (double)(first + 1) / (double)(G + 1);
         ga[grp] = xa;
@@ -148,74 +247,18 @@ __device__ void tridiag_top(const double* al, const double* be, int k, int nr, d
   if (t < nr) theta[t] = 0.5 * (ga[t] + gb[t]);
   __syncthreads();
 
-  // eigenvectors by inverse iteration (thread tt owns vector tt)
+  // eigenvectors by inverse iteration (thread tt owns vector tt); the shift
+  // is accurate to a few ulps of |T|, so two sweeps from a random start
+  // leave an error of order eps |T| / gap
   const double pert = eps * fmax(tnorm, DBL_MIN) + pivmin;
   const double cluster_gap = 1e-3 * tnorm;
-  for (int it = 0; it < 3; ++it) {
-    if (t < nr) {
-      double* z = Z + (int64_t)t * ldz;
-      const double th = theta[t];
-      // factor T - th I with partial pivoting, applying the row operations to
-      // the right-hand side on the fly; keep U (dd, u1, u2) and the
-      // eliminated right-hand side y for the backward pass.
-      double zc = (it == 0) ? 1.0 + 0.5 * hash_unit(0, 977 + t) : z[0];
-      double cur_d = al[0] - th;
-      double cur_u = (k > 1) ? be[0] : 0.0;
-      double cur_u2 = 0.0;
-      for (int i = 0; i < k - 1; ++i) {
-        const double sub = be[i];
-        const double nd = al[i + 1] - th;
-        const double nu = (i + 1 < k - 1) ? be[i + 1] : 0.0;
-        const double zn = (it == 0) ? 1.0 + 0.5 * hash_unit((uint64_t)(i + 1), 977 + t) : z[i + 1];
-        double di, u1, u2, y;
-        if (fabs(cur_d) >= fabs(sub)) {
-          di = (cur_d == 0.0) ? pert : cur_d;
-          const double mlt = sub / di;
-          u1 = cur_u;
-          u2 = cur_u2;
-          y = zc;
-          zc = zn - mlt * zc;
-          cur_d = nd - mlt * cur_u;
-          cur_u = nu - mlt * cur_u2;
-        } else {
-          const double mlt = cur_d / sub;
-          di = sub;
-          u1 = nd;
-          u2 = nu;
-          y = zn;
-          zc = zc - mlt * zn;
-          const double nd2 = cur_u - mlt * nd;
-          const double nu2 = cur_u2 - mlt * nu;
-          cur_d = nd2;
-          cur_u = nu2;
-        }
-        cur_u2 = 0.0;
-        wk[((int64_t)i * 4 + 0) * nr + t] = di;
-        wk[((int64_t)i * 4 + 1) * nr + t] = u1;
-        wk[((int64_t)i * 4 + 2) * nr + t] = u2;
-        wk[((int64_t)i * 4 + 3) * nr + t] = y;
-      }
-      double dl = (cur_d == 0.0) ? pert : cur_d;
-      if (fabs(dl) < pert) dl = (dl < 0 ? -pert : pert);
-      // backward substitution with a rolling window of two values
-      double z1 = zc / dl, z2 = 0.0;
-      double nn = z1 * z1;
-      z[k - 1] = z1;
-      for (int i = k - 2; i >= 0; --i) {
-        double di = wk[((int64_t)i * 4 + 0) * nr + t];
-        const double u1 = wk[((int64_t)i * 4 + 1) * nr + t];
-        const double u2 = wk[((int64_t)i * 4 + 2) * nr + t];
-        const double y = wk[((int64_t)i * 4 + 3) * nr + t];
-        if (fabs(di) < pert) di = (di < 0 ? -pert : pert);
-        const double zi = (y - u1 * z1 - u2 * z2) / di;
-        z2 = z1;
-        z1 = zi;
-        z[i] = zi;
-        nn = fma(zi, zi, nn);
-      }
-      const double inv = 1.0 / sqrt(nn);
-      for (int i = 0; i < k; ++i) z[i] *= inv;
-    }
+  for (int e = t; e < k * nr; e += NT) {  // random start vectors
+    const int tt = e / k, i = e % k;
+    Z[(int64_t)tt * ldz + i] = 1.0 + 0.5 * hash_unit((uint64_t)i, 977 + tt);
+  }
+  __syncthreads();
+  for (int it = 0; it < 2; ++it) {
+    if (t < nr) inverse_sweep(al, be, k, theta[t], pert, Z + (int64_t)t * ldz, wk + t, nr);
     __syncthreads();
     // modified Gram-Schmidt inside clusters of close eigenvalues
     for (int tt = 1; tt < nr; ++tt) {
@@ -227,16 +270,16 @@ __device__ void tridiag_top(const double* al, const double* be, int k, int nr, d
         if (fabs(theta[tt] - theta[ss]) > cluster_gap) continue;
         const double* zs = Z + (int64_t)ss * ldz;
         double d = 0.0;
-        for (int i = t; i < k; i += 256) d = fma(zs[i], zt[i], d);
-        d = block_sum4(d, sh4);
-        for (int i = t; i < k; i += 256) zt[i] -= d * zs[i];
+        for (int i = t; i < k; i += NT) d = fma(zs[i], zt[i], d);
+        d = block_sum_n<NT>(d, shw);
+        for (int i = t; i < k; i += NT) zt[i] -= d * zs[i];
         __syncthreads();
       }
       double nn = 0.0;
-      for (int i = t; i < k; i += 256) nn = fma(zt[i], zt[i], nn);
-      nn = block_sum4(nn, sh4);
+      for (int i = t; i < k; i += NT) nn = fma(zt[i], zt[i], nn);
+      nn = block_sum_n<NT>(nn, shw);
       const double inv = 1.0 / sqrt(nn);
-      for (int i = t; i < k; i += 256) zt[i] *= inv;
+      for (int i = t; i < k; i += NT) zt[i] *= inv;
       __syncthreads();
     }
   }
