@@ -20,8 +20,9 @@ Pin status (what fixes each part independently of this code):
 No function is left "parity unpinned".
 """
 
-from .mds import (TAU, DegenerateError, Fit, classical_mds, fit_from_sqdist, fit_landmarks,
-                  gower_block, inner_products, interpolate, interpolate_sqdist, interpolation_mds,
+from .mds import (TAU, DegenerateError, Fit, affine_map, classical_mds, fit_from_sqdist, fit_landmarks,
+                  gower_block, inner_products, interpolate, interpolate_affine, interpolate_sqdist,
+                  interpolation_mds,
                   interpolation_mds_paper_layout, lmds_block, sign_convention,
                   sqdist_rows, sqdist_rows_expanded, top_eigenpairs)
 from .sampler import SplitMix64, bounded, fisher_yates_prefix, sample_landmarks
@@ -29,7 +30,8 @@ from .linalg_small import jacobi_eigh, procrustes
 from . import dc
 
 __all__ = [
-    "TAU", "DegenerateError", "Fit", "classical_mds", "fit_from_sqdist", "fit_landmarks",
+    "TAU", "DegenerateError", "Fit", "affine_map", "classical_mds", "fit_from_sqdist", "fit_landmarks",
+    "interpolate_affine",
     "interpolate_sqdist",
     "gower_block", "inner_products", "interpolate", "interpolation_mds",
     "interpolation_mds_paper_layout", "lmds_block", "sign_convention",

@@ -213,6 +213,28 @@ def interpolate_sqdist(fit, A2, formula=None):
     return formula(fit, np.asarray(A2, dtype=np.float64))
 
 
+def affine_map(fit):
+    """For squared Euclidean distances eq. (2) is an affine map of x.  With
+    the centred landmarks Mc = M - 1 mbar' (mbar their mean) classical MDS of
+    the landmarks is their principal-component analysis (Section 2), and
+    Gower's formula is the projection y = Lambda^{-1/2} V' Mc (x - mbar)
+    (derived from eq. (2) with V'1 = 0).  Returns (A, b) with y = A x + b:
+    A = Lambda^{-1/2} V' Mc (r x p), b = -A mbar; dead columns give zero
+    rows."""
+    M = fit.M
+    mbar = M.mean(axis=0)
+    scale = np.where(fit.live, 1.0 / np.sqrt(np.where(fit.live, fit.lam, 1.0)), 0.0)
+    A = scale[:, None] * (fit.V.T @ (M - mbar))
+    return A, -A @ mbar
+
+
+def interpolate_affine(fit, Xnew):
+    """Rows of Xnew through the affine form of eq. (2) (Euclidean input
+    only); every row, in input order."""
+    A, b = affine_map(fit)
+    return np.asarray(Xnew, dtype=np.float64) @ A.T + b
+
+
 def interpolation_mds(X, l, r, seed=0, idx=None):
     """Interpolation MDS of the data X: fit on l landmarks, then interpolate
     all n rows (landmarks included) in input order."""
