@@ -269,6 +269,32 @@ def sqdist_leg(mds, torch, model, Xd, Y32, iters):
             "rms_rel_vs_fp32_embed": err["rms_rel"]}
 
 
+def affine_leg(mds, torch, model, Xd, Y64, iters):
+    """mds_embed_affine (y = A x + b, squared Euclidean only) on the same
+    rows and model, FP32: a streaming kernel, reported against the HBM
+    peak, with its error against the FP64 distance path."""
+    from synth import errors
+    st = torch.cuda.current_stream()
+    Y = mds.embed_affine(model, Xd, prec="fp32")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(iters):
+        mds.embed_affine(model, Xd, prec="fp32", Y=Y)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / iters
+    n, p = Xd.shape
+    nbytes = 4.0 * n * (p + model.r)
+    e = errors.column_errors(Y.cpu().numpy(), Y64)
+    return {"ms": t * 1e3, "points_per_s": n / t,
+            "roofline": {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM / 1e9,
+                         "unit": "GB/s", "frac": nbytes / t / PEAK_HBM, "bytes_per_launch": nbytes},
+            "err_vs_gpu_fp64_distance_path": {k: e[k] for k in ("rms_rel", "maxabs_rms")},
+            "note": "separate mode (affine form of eq. (2)); not the distance-block path"}
+
+
 DC = dict(n=1_000_000, k=100, h=10, l=400, c=50, r=10,
           desc="divide-and-conquer MDS, 1,000,000 x 100 rows of the simulation design "
                "(10 columns of variance 15, 90 of variance 1), l=400, c=5r=50, r=10; "
@@ -386,6 +412,7 @@ def main():
     ap.add_argument("--only-fit", action="store_true", help="run --iters fits only (profiling)")
     ap.add_argument("--copy-calib", type=int, default=0)
     ap.add_argument("--no-dc", action="store_true")
+    ap.add_argument("--no-affine", action="store_true")
     ap.add_argument("--dc-iters", type=int, default=5)
     ap.add_argument("--only-dc", action="store_true", help="run --iters divide-and-conquer calls only")
     args = ap.parse_args()
@@ -511,6 +538,9 @@ def main():
     if args.workload == "wide" and not args.no_sqdist:
         log("embedding from squared dissimilarities")
         out["embed_from_sqdist"] = sqdist_leg(mds, torch, model, Xd, Y32, args.embed_iters)
+    if not args.no_affine:
+        log("affine form")
+        out["embed_affine"] = affine_leg(mds, torch, model, Xd, Y64n, args.embed_iters)
     if args.workload == "wide" and not args.no_dc:
         log("divide-and-conquer MDS")
         out["divide_conquer"] = dc_leg(mds, torch, args.dc_iters, not args.no_cpu_baseline)

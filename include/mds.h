@@ -144,6 +144,22 @@ mds_status mds_fit_from_sqdist(const double* D1, int64_t l, int64_t ldd, int32_t
 mds_status mds_embed_from_sqdist(const mds_model* m, const void* A2, int32_t dt, int64_t n_new,
                                  int64_t lda, int32_t prec, void* Y, int64_t ldy, void* stream);
 
+/* ---- affine form of eq. (2) for squared Euclidean distances ------------
+ * Eq. (2) reads y = W'(c - |x|^2 1 + 2 M x) with W = 1/2 V Lambda^{-1/2}
+ * and c = q1 - |m|^2; the columns of V sum to zero (Q1 1 = 0, Section 2),
+ * so y = A x + b with A = 2 W' M and b = W' c, formed in FP64 at fit time.
+ * This is the same map as mds_embed in exact arithmetic (the landmark
+ * principal-component projection, since classical MDS of Euclidean
+ * vectors is their PCA), at 2 p r flops per row instead of 2 l (p + r).
+ * It is a separate mode: it does not evaluate the distances of eq. (2).
+ * Arguments as mds_embed; prec is MDS_PREC_FP64 (Y double, X F32 or F64)
+ * or MDS_PREC_FP32 (Y float, X F32).  Asynchronous on `stream`; a
+ * memory-bound streaming kernel.  n_new == 0 is a no-op.
+ * Errors: INVALID_ARG (null pointers, model fitted on dissimilarities,
+ * ldx < p, ldy < r, dt/prec mismatch), HIP. */
+mds_status mds_embed_affine(const mds_model* m, const void* X, int32_t dt, int64_t n_new,
+                            int64_t ldx, int32_t prec, void* Y, int64_t ldy, void* stream);
+
 /* ---- divide-and-conquer MDS (Section 3.2) ------------------------------
  * The rows are split at random into parts that share c connecting points;
  * classical MDS (Section 2) runs on every part and each part's

@@ -5,8 +5,8 @@ package only marshals arguments.  There is no CPU fallback: if the library
 is missing every call raises.
 """
 
-from .api import (F32, F64, PREC, MDSError, Model, divide_conquer, embed, embed_from_sqdist,
+from .api import (F32, F64, PREC, MDSError, Model, divide_conquer, embed, embed_affine, embed_from_sqdist,
                   fit_from_sqdist, fit_landmarks, free, sample_landmarks)
 
-__all__ = ["F32", "F64", "PREC", "MDSError", "Model", "divide_conquer", "embed", "embed_from_sqdist",
+__all__ = ["F32", "F64", "PREC", "MDSError", "Model", "divide_conquer", "embed", "embed_affine", "embed_from_sqdist",
            "fit_from_sqdist", "fit_landmarks", "free", "sample_landmarks"]

@@ -220,6 +220,24 @@ def embed_from_sqdist(model, A2, prec="fp32", Y=None, stream=None):
     return Y
 
 
+def embed_affine(model, X, prec="fp32", Y=None, stream=None):
+    """mds_embed_affine: eq. (2) in its affine form y = A x + b (squared
+    Euclidean distances only; a separate mode, not the distance path)."""
+    import torch
+    _check_matrix(X, "X")
+    n = X.shape[0]
+    code = PREC[prec]
+    ydt = torch.float64 if code == PREC["fp64"] else torch.float32
+    if Y is None:
+        Y = torch.empty((n, model.r), dtype=ydt, device=X.device)
+    ldx = X.stride(0) if n > 1 else X.shape[1]
+    ldy = Y.stride(0) if n > 1 else Y.shape[1]
+    _check(_lib.lib().mds_embed_affine(model.handle, ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n,
+                                       ldx, code, ctypes.c_void_p(Y.data_ptr()), ldy,
+                                       _stream_ptr(stream)))
+    return Y
+
+
 def divide_conquer(X, l, c, r, seed=0, Y=None, return_order=False, stream=None):
     """mds_divide_conquer (Section 3.2): divide-and-conquer MDS of the rows
     of X (n x p device tensor, float32 or float64).  Returns (Y, lam_bar,

@@ -265,6 +265,28 @@ mds_status mds_fit_from_sqdist(const double* D1, int64_t l, int64_t ldd, int32_t
   return MDS_OK;
 }
 
+mds_status mds_embed_affine(const mds_model* h, const void* X, int32_t dt, int64_t n_new, int64_t ldx,
+                            int32_t prec, void* Y, int64_t ldy, void* stream) {
+  if (!h) return set_error(MDS_ERR_INVALID_ARG, "model is NULL");
+  const Model& m = h->m;
+  if (!m.vectors)
+    return set_error(MDS_ERR_INVALID_ARG,
+                     "model was fitted on dissimilarities: the affine form needs landmark vectors");
+  if (n_new < 0) return set_error(MDS_ERR_INVALID_ARG, "n_new < 0");
+  if (prec != MDS_PREC_FP64 && prec != MDS_PREC_FP32)
+    return set_error(MDS_ERR_INVALID_ARG, "the affine form takes FP64 or FP32");
+  if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
+  if (prec == MDS_PREC_FP32 && dt != MDS_F32)
+    return set_error(MDS_ERR_INVALID_ARG, "FP32 precision takes MDS_F32 input");
+  if (n_new == 0) return MDS_OK;
+  if (!X || !Y) return set_error(MDS_ERR_INVALID_ARG, "X or Y is NULL");
+  if (ldx < m.p) return set_error(MDS_ERR_INVALID_ARG, "ldx < p");
+  if (ldy < m.r) return set_error(MDS_ERR_INVALID_ARG, "ldy < r");
+  if (n_new > ((int64_t)1 << 36)) return set_error(MDS_ERR_INVALID_ARG, "n_new too large");
+  return launch_embed_affine(m, prec == MDS_PREC_FP64 ? 1 : 0, X, dt, n_new, ldx, Y, ldy,
+                             reinterpret_cast<hipStream_t>(stream));
+}
+
 mds_status mds_divide_conquer(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
                               int64_t c, int32_t r, uint64_t seed, double* Y, int64_t ldy,
                               double* lam_bar, int32_t* r_eff, int64_t* order_out, void* stream) {

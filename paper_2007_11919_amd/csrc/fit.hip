@@ -426,6 +426,42 @@ __global__ __launch_bounds__(256) void k_bias(const double* __restrict__ M, int6
 
 // q as FP64 and FP32 (zero for padding landmarks), for embedding from
 // dissimilarities
+// Affine form of eq. (2) for Euclidean input: y = A x + b with
+// A[k][i] = 2 sum_j W[j][k] M[j][i] and b[k] = sum_j W[j][k] c[j] (the
+// |x|^2 term drops out because the columns of V sum to zero).  Column i == p
+// of the grid computes b.  A block covers 64 columns of one output k; its
+// four waves take the landmarks j = w (mod 4), combined in order.
+__global__ __launch_bounds__(256) void k_affine_map(const double* __restrict__ M, int64_t ldm,
+                                                    int64_t l, int64_t p,
+                                                    const double* __restrict__ W, int ldw,
+                                                    const double* __restrict__ c, int r,
+                                                    double* __restrict__ A64, float* __restrict__ A32,
+                                                    double* __restrict__ b64, float* __restrict__ b32) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int k = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (i <= p) {
+    if (i < p)
+      for (int64_t j = g; j < l; j += 4) acc = fma(W[j * ldw + k], M[j * ldm + i], acc);
+    else
+      for (int64_t j = g; j < l; j += 4) acc = fma(W[j * ldw + k], c[j], acc);
+  }
+  part[g][lane] = acc;
+  __syncthreads();
+  if (g == 0 && i <= p) {
+    const double s = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (i < p) {
+      A64[(int64_t)k * p + i] = 2.0 * s;
+      A32[(int64_t)k * p + i] = (float)(2.0 * s);
+    } else {
+      b64[k] = s;
+      b32[k] = (float)s;
+    }
+  }
+}
+
 __global__ void k_copy_q(const double* __restrict__ q, int64_t l, int64_t l_pad,
                          double* __restrict__ q64, float* __restrict__ q32) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -563,6 +599,10 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   const size_t oc64 = lay.take(sizeof(double) * l_pad);
   const size_t oq32 = lay.take(sizeof(float) * l_pad);
   const size_t oq64 = lay.take(sizeof(double) * l_pad);
+  const size_t oa64 = lay.take(sizeof(double) * (size_t)r * p);
+  const size_t oa32 = lay.take(sizeof(float) * (size_t)r * p);
+  const size_t ob64 = lay.take(sizeof(double) * (size_t)r);
+  const size_t ob32 = lay.take(sizeof(float) * (size_t)r);
   m.base = model_alloc(m.dev, lay.off);
   if (!m.base) return set_error(MDS_ERR_OOM, "device allocation of the model failed");
   char* b = static_cast<char*>(m.base);
@@ -576,6 +616,10 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   m.c64 = b + oc64;
   m.q32 = b + oq32;
   m.q64 = b + oq64;
+  m.aff64 = b + oa64;
+  m.aff32 = b + oa32;
+  m.affb64 = b + ob64;
+  m.affb32 = b + ob32;
   m.bytes = (int64_t)lay.off;
   MDS_HIP(hipMemsetAsync(m.base, 0, lay.off, st));
 
@@ -800,6 +844,10 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     k_pack32<<<grid, 256, 0, st>>>((const double*)m.m64, ldm, l_pad, p, nch32, (float*)m.m32,
                                    (uint16_t*)m.mbf, (uint16_t*)m.mh, scales, ctrl + 4);
+    dim3 agrid((unsigned)((p + 1 + 63) / 64), (unsigned)r);
+    k_affine_map<<<agrid, 256, 0, st>>>((const double*)m.m64, ldm, l, p, (const double*)m.w64, ldw,
+                                        (const double*)m.c64, r, (double*)m.aff64, (float*)m.aff32,
+                                        (double*)m.affb64, (float*)m.affb32);
   } else {
     k_scale<<<1, 256, 0, st>>>(rowmax, 0, scales);  // unused without vectors
   }

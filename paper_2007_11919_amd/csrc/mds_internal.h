@@ -77,6 +77,10 @@ struct Model {
   void* c64 = nullptr;    // l_pad double
   void* q32 = nullptr;    // l_pad float: diag(Q1), for embedding from dissimilarities
   void* q64 = nullptr;    // l_pad double
+  void* aff64 = nullptr;  // r x p double: A = 2 W' M of the affine form y = A x + b
+  void* aff32 = nullptr;  // r x p float
+  void* affb64 = nullptr; // r double: b = W' c
+  void* affb32 = nullptr; // r float
   bool vectors = true;    // fitted on data rows (false: on a dissimilarity matrix)
   int bf_lo_zero = 0, h_lo_zero = 0;
   float h_prescale = 1.f, h_postscale = 1.f;
@@ -116,6 +120,10 @@ mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t
 mds_status dc_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int64_t c,
                         int r, uint64_t seed, double* Y, int64_t ldy, double* lam_bar, int32_t* r_eff,
                         int64_t* order_out, hipStream_t st);
+// y = A x + b for rows of X (embed_affine.hip); prec64: FP64 arithmetic and
+// double Y, else FP32 arithmetic and float Y (X float).
+mds_status launch_embed_affine(const Model& m, int prec64, const void* X, int dt, int64_t n,
+                               int64_t ldx, void* Y, int64_t ldy, hipStream_t st);
 mds_status launch_embed_sqdist(const Model& m, int prec64, const void* A2, int dt, int64_t n,
                                int64_t lda, void* Y, int64_t ldy, hipStream_t st);
 // persistent serving launch over a device table of tiles
