@@ -17,6 +17,13 @@ Pin status (what fixes each part independently of this code):
                   vector path on Euclidean input; brute-force Jacobi on a
                   non-Euclidean matrix; self-reproduction and Proposition 1
                   for non-Euclidean input.
+* MaxMin and pivot MDS (oracle.pivot, Section 3.1) - MaxMin checked step
+                  by step by brute force and on a line whose sequence is
+                  known; pivot MDS with every point a pivot is brute-force
+                  Jacobi classical MDS; the double-centred block equals the
+                  inner products of centred points and pivots; the
+                  configuration spans the centred data; Section 4.1
+                  eigenvalue estimates and correlations.
 No function is left "parity unpinned".
 """
 
@@ -28,6 +35,7 @@ from .mds import (TAU, DegenerateError, Fit, affine_map, classical_mds, fit_from
 from .sampler import SplitMix64, bounded, fisher_yates_prefix, sample_landmarks
 from .linalg_small import jacobi_eigh, procrustes
 from . import dc
+from . import pivot
 
 __all__ = [
     "TAU", "DegenerateError", "Fit", "affine_map", "classical_mds", "fit_from_sqdist", "fit_landmarks",
@@ -37,5 +45,5 @@ __all__ = [
     "interpolation_mds_paper_layout", "lmds_block", "sign_convention",
     "sqdist_rows", "sqdist_rows_expanded", "top_eigenpairs", "SplitMix64",
     "bounded", "fisher_yates_prefix", "sample_landmarks", "jacobi_eigh",
-    "procrustes", "dc",
+    "procrustes", "dc", "pivot",
 ]
