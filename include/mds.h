@@ -144,6 +144,46 @@ mds_status mds_fit_from_sqdist(const double* D1, int64_t l, int64_t ldd, int32_t
 mds_status mds_embed_from_sqdist(const mds_model* m, const void* A2, int32_t dt, int64_t n_new,
                                  int64_t lda, int32_t prec, void* Y, int64_t ldy, void* stream);
 
+/* ---- MaxMin landmark selection (the landmark choice of LMDS, Section 3.1)
+ * From row `first`, repeatedly add the row whose smallest squared
+ * Euclidean distance to the rows chosen so far is largest (smallest row
+ * index on ties).  Each squared distance is summed in FP64 over the columns
+ * in order, one rounded product and one rounded sum per column, so the
+ * choices do not depend on the launch shape.  One pass over X per landmark.
+ * X: device, n x p rows, leading dimension ldx >= p, element type dt.
+ * idx_out: host, l int64 (caller-owned), in selection order.  The result
+ * can be passed to mds_fit_landmarks (LMDS = this choice of landmarks plus
+ * Gower's formula, by Proposition 1) or mds_pivot_mds.  Synchronous.
+ * Errors: INVALID_ARG (pointers, sizes, first outside [0, n)), DEGENERATE
+ * (fewer than l distinct rows), OOM, HIP. */
+mds_status mds_maxmin_landmarks(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx,
+                                int64_t l, int64_t first, int64_t* idx_out, void* stream);
+
+/* ---- pivot MDS (Section 3.1) ---------------------------------------------
+ * With l pivot rows, C is the double-centred n x l block of squared
+ * distances between all rows and the pivots, and its singular value
+ * decomposition C = U Sigma W' stands in for the eigendecomposition of Q:
+ * lambda_k = sigma_k sqrt(n / l) estimates Q's eigenvalues (exact when the
+ * pivots are all the rows) and Y = U_r Lambda_r^{1/2}.  The sign of column
+ * k follows W's column k (largest-|.| entry positive, first pivot on ties);
+ * direction k is live when sigma_k^2 > MDS_TAU * sigma_1^2 (the eigenvalue
+ * test on C'C, whose eigenvalues are computed); dead columns are zero and
+ * report lambda = 0.  Dissimilarities
+ * are squared Euclidean distances, for which C = Xc Mc' (rows and pivots
+ * centred on their means); the work is computed through that identity in
+ * FP64 (means, p x p cross-product, l x l eigenproblem, one streaming pass).
+ * Pivots: idx_or_null (host, l distinct rows, e.g. from
+ * mds_maxmin_landmarks), else mds_sample_landmarks(n, l, seed).  The scale
+ * estimate assumes pivots representative of the data, as random ones are.
+ * X as for mds_maxmin_landmarks; 2 <= l <= min(n, MDS_DC_MAX_L),
+ * 1 <= r <= min(l - 1, MDS_MAX_R), p <= 4096.  Y: device, n x r doubles,
+ * ldy >= r.  lam: host, r doubles (may be NULL); r_eff: host (may be NULL).
+ * Synchronous.  Errors: INVALID_ARG (pointers, sizes, bad pivots, non-finite
+ * X), DEGENERATE (lambda_1 <= 0), OOM, HIP. */
+mds_status mds_pivot_mds(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
+                         int32_t r, uint64_t seed, const int64_t* idx_or_null, double* Y,
+                         int64_t ldy, double* lam, int32_t* r_eff, void* stream);
+
 /* ---- affine form of eq. (2) for squared Euclidean distances ------------
  * Eq. (2) reads y = W'(c - |x|^2 1 + 2 M x) with W = 1/2 V Lambda^{-1/2}
  * and c = q1 - |m|^2; the columns of V sum to zero (Q1 1 = 0, Section 2),

@@ -84,7 +84,61 @@ def pivot_mds(X, idx, r):
     lam = s * np.sqrt(n / l)
     if not lam[0] > 0:
         raise DegenerateError("largest eigenvalue is not positive")
-    live = lam > TAU * lam[0]
+    live = s * s > TAU * s[0] * s[0]
+    lam = np.where(live, lam, 0.0)
     Y = np.zeros((n, len(lam)))
     Y[:, live] = U[:, live] * np.sqrt(lam[live])
+    return Y, lam, W
+
+
+def pivot_mds_large(X, idx, r, rows=None, chunk=65536):
+    """Pivot MDS for large n without holding the n x l block: squared
+    distances by the oracle's centred FP64 expansion (sqdist_rows_expanded),
+    C'C accumulated over row chunks, its eigenpairs (sigma^2, W), then
+    Y = C W Sigma^{-1} Lambda^{1/2} for the requested rows only (all when
+    rows is None).  Same readings as pivot_mds; returns (Y_rows, lam, W)."""
+    from .mds import sqdist_rows_expanded
+    X = np.asarray(X)
+    n, l = X.shape[0], len(idx)
+    M = np.asarray(X[idx], dtype=np.float64)
+    colsum = np.zeros(l)
+    tot = 0.0
+    for s in range(0, n, chunk):
+        D = sqdist_rows_expanded(X[s:s + chunk].astype(np.float64), M)
+        colsum += D.sum(axis=0)
+        tot += D.sum()
+    colmean = colsum / n
+    grand = tot / (n * l)
+
+    def block(s, e):
+        D = sqdist_rows_expanded(X[s:e].astype(np.float64), M)
+        return -0.5 * (D - D.mean(axis=1)[:, None] - colmean[None, :] + grand)
+
+    CtC = np.zeros((l, l))
+    for s in range(0, n, chunk):
+        C = block(s, min(n, s + chunk))
+        CtC += C.T @ C
+    th, V = np.linalg.eigh(0.5 * (CtC + CtC.T))
+    order = np.argsort(-th, kind="stable")[:r]
+    th = th[order]
+    W = V[:, order].copy()
+    for k in range(r):
+        i = int(np.argmax(np.abs(W[:, k])))
+        if W[i, k] < 0:
+            W[:, k] = -W[:, k]
+    sigma = np.sqrt(np.maximum(th, 0.0))
+    lam = sigma * np.sqrt(n / l)
+    if not lam[0] > 0:
+        raise DegenerateError("largest eigenvalue is not positive")
+    live = th > TAU * th[0]
+    lam = np.where(live, lam, 0.0)
+    fac = np.zeros(r)
+    fac[live] = np.sqrt(lam[live]) / sigma[live]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    Y = np.empty((len(rows), r))
+    for s in range(0, len(rows), chunk):
+        sel = rows[s:s + chunk]
+        D = sqdist_rows_expanded(X[sel].astype(np.float64), M)
+        C = -0.5 * (D - D.mean(axis=1)[:, None] - colmean[None, :] + grand)
+        Y[s:s + chunk] = (C @ W) * fac[None, :]
     return Y, lam, W

@@ -220,6 +220,39 @@ def embed_from_sqdist(model, A2, prec="fp32", Y=None, stream=None):
     return Y
 
 
+def maxmin_landmarks(X, l, first=0, stream=None):
+    """mds_maxmin_landmarks: l row indices of X chosen by MaxMin from row
+    `first`, in selection order (numpy int64)."""
+    _check_matrix(X, "X")
+    n, p = X.shape
+    out = np.empty(l, dtype=np.int64)
+    ldx = X.stride(0) if n > 1 else p
+    _check(_lib.lib().mds_maxmin_landmarks(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n, p, ldx, l,
+                                           first, out.ctypes.data_as(_lib.P_i64), _stream_ptr(stream)))
+    return out
+
+
+def pivot_mds(X, l, r, seed=0, idx=None, Y=None, stream=None):
+    """mds_pivot_mds: pivot MDS of the rows of X; returns (Y, lam, r_eff)."""
+    import torch
+    _check_matrix(X, "X")
+    n, p = X.shape
+    if Y is None:
+        Y = torch.empty((n, r), dtype=torch.float64, device=X.device)
+    ldx = X.stride(0) if n > 1 else p
+    ldy = Y.stride(0) if n > 1 else r
+    lam = (ctypes.c_double * r)()
+    r_eff = ctypes.c_int32(0)
+    idx_arr = None
+    if idx is not None:
+        idx_arr = np.ascontiguousarray(idx, dtype=np.int64)
+    _check(_lib.lib().mds_pivot_mds(
+        ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n, p, ldx, l, r, seed,
+        idx_arr.ctypes.data_as(_lib.P_i64) if idx_arr is not None else None,
+        ctypes.c_void_p(Y.data_ptr()), ldy, lam, ctypes.byref(r_eff), _stream_ptr(stream)))
+    return Y, np.array(lam[:], dtype=np.float64), int(r_eff.value)
+
+
 def embed_affine(model, X, prec="fp32", Y=None, stream=None):
     """mds_embed_affine: eq. (2) in its affine form y = A x + b (squared
     Euclidean distances only; a separate mode, not the distance path)."""

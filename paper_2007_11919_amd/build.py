@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmds.so")
 
-SOURCES = ["api.cpp", "sampler.cpp", "serve.cpp", "fit.hip", "embed.hip", "embed_sqdist.hip", "embed_affine.hip", "dc.hip"]
+SOURCES = ["api.cpp", "sampler.cpp", "serve.cpp", "fit.hip", "embed.hip", "embed_sqdist.hip", "embed_affine.hip", "dc.hip", "pivot.hip"]
 ARCH = "gfx950"
 
 COMMON = [

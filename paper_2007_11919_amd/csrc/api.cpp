@@ -265,6 +265,55 @@ mds_status mds_fit_from_sqdist(const double* D1, int64_t l, int64_t ldd, int32_t
   return MDS_OK;
 }
 
+mds_status mds_maxmin_landmarks(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
+                                int64_t first, int64_t* idx_out, void* stream) {
+  if (!X || !idx_out) return set_error(MDS_ERR_INVALID_ARG, "X or idx_out is NULL");
+  if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
+  if (p < 1 || ldx < p) return set_error(MDS_ERR_INVALID_ARG, "need p >= 1 and ldx >= p");
+  if (l < 1 || l > n) return set_error(MDS_ERR_INVALID_ARG, "need 1 <= l <= n");
+  if (first < 0 || first >= n) return set_error(MDS_ERR_INVALID_ARG, "first out of range");
+  if (n > ((int64_t)1 << 36)) return set_error(MDS_ERR_INVALID_ARG, "n too large");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  mds_status s = maxmin_on_device(X, dt, n, p, ldx, l, first, idx_out, st);
+  if (s != MDS_OK) (void)hipStreamSynchronize(st);
+  return s;
+}
+
+mds_status mds_pivot_mds(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int32_t r,
+                         uint64_t seed, const int64_t* idx_or_null, double* Y, int64_t ldy, double* lam,
+                         int32_t* r_eff, void* stream) {
+  if (!X || !Y) return set_error(MDS_ERR_INVALID_ARG, "X or Y is NULL");
+  if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
+  if (p < 1 || ldx < p) return set_error(MDS_ERR_INVALID_ARG, "need p >= 1 and ldx >= p");
+  if (p > 4096) return set_error(MDS_ERR_INVALID_ARG, "p too large (max 4096)");
+  if (l < 2 || l > n) return set_error(MDS_ERR_INVALID_ARG, "need 2 <= l <= n");
+  if (l > MDS_DC_MAX_L) return set_error(MDS_ERR_INVALID_ARG, "l too large (max 2048)");
+  if (r < 1 || r > l - 1 || r > MDS_MAX_R)
+    return set_error(MDS_ERR_INVALID_ARG, "need 1 <= r <= min(l - 1, MDS_MAX_R)");
+  if (ldy < r) return set_error(MDS_ERR_INVALID_ARG, "ldy < r");
+  if (n > ((int64_t)1 << 36)) return set_error(MDS_ERR_INVALID_ARG, "n too large");
+  std::vector<int64_t> idx((size_t)l);
+  try {
+    if (idx_or_null) {
+      std::vector<int64_t> v(idx_or_null, idx_or_null + l);
+      std::sort(v.begin(), v.end());
+      for (int64_t i = 0; i < l; ++i) {
+        if (v[i] < 0 || v[i] >= n) return set_error(MDS_ERR_INVALID_ARG, "pivot index out of range");
+        if (i > 0 && v[i] == v[i - 1]) return set_error(MDS_ERR_INVALID_ARG, "duplicate pivot index");
+      }
+      std::memcpy(idx.data(), idx_or_null, sizeof(int64_t) * l);  // the caller's order
+    } else {
+      sample_landmarks_host(n, l, seed, idx.data());
+    }
+  } catch (const std::bad_alloc&) {
+    return set_error(MDS_ERR_OOM, "host allocation failed");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  mds_status s = pivot_on_device(X, dt, n, p, ldx, l, r, idx.data(), Y, ldy, lam, r_eff, st);
+  if (s != MDS_OK) (void)hipStreamSynchronize(st);
+  return s;
+}
+
 mds_status mds_embed_affine(const mds_model* h, const void* X, int32_t dt, int64_t n_new, int64_t ldx,
                             int32_t prec, void* Y, int64_t ldy, void* stream) {
   if (!h) return set_error(MDS_ERR_INVALID_ARG, "model is NULL");

@@ -822,6 +822,45 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
 
 }  // namespace
 
+mds_status dense_top_eigen(double* G, int d, int r, double* lam, double* U, int* status,
+                           hipStream_t st) {
+  DcShape s;
+  s.n = d;
+  s.p = d;
+  s.l = d;
+  s.c = 0;
+  s.r = r;
+  s.nparts = 1;
+  s.m_max = d;
+  const int nr = std::min(r, d);
+  static bool attr_set = false;
+  if (!attr_set) {
+    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
+    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
+    attr_set = true;
+  }
+  if (eigen_lds_bytes(d, nr) <= kDcLdsMax) {
+    k_dc_eigen<true><<<1, DC_NT, eigen_lds_bytes(d, nr), st>>>(G, d, s, 0, 0, nr, nullptr, nullptr,
+                                                              nullptr, lam, U, nullptr, status);
+  } else {
+    DevMem zg, wkg, partg;
+    auto alloc = [&](DevMem& b, size_t bytes) -> hipError_t {
+      b.st = st;
+      return hipMallocAsync(&b.p, std::max<size_t>(bytes, 256), st);
+    };
+    DC_HIP(alloc(zg, sizeof(double) * nr * (size_t)d));
+    DC_HIP(alloc(wkg, sizeof(double) * 4 * (size_t)d * nr));
+    DC_HIP(alloc(partg, sizeof(double) * DC_NW * (size_t)d));
+    k_dc_eigen<false><<<1, DC_NT, sizeof(double) * 5 * (size_t)d, st>>>(
+        G, d, s, 0, 0, nr, zg.get<double>(), wkg.get<double>(), partg.get<double>(), lam, U, nullptr,
+        status);
+  }
+  DC_LAUNCH("dense eigensolver");
+  return MDS_OK;
+}
+
 mds_status dc_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int64_t c,
                         int r, uint64_t seed, double* Y, int64_t ldy, double* lam_bar, int32_t* r_eff,
                         int64_t* order_out, hipStream_t st) {

@@ -199,36 +199,43 @@ void launch_af_rb(const TX* x, int64_t n, int64_t ldx, int64_t p, const T* A, co
 }
 
 template <typename TX, typename T>
-hipError_t launch_af(const Model& m, const void* X, int64_t n, int64_t ldx, void* Y, int64_t ldy,
-                     hipStream_t st) {
-  const bool f64 = std::is_same<T, double>::value;
-  const T* A = static_cast<const T*>(f64 ? m.aff64 : m.aff32);
-  const T* b = static_cast<const T*>(f64 ? m.affb64 : m.affb32);
+hipError_t launch_af(const T* A, const T* b, int64_t p, int r, const void* X, int64_t n, int64_t ldx,
+                     void* Y, int64_t ldy, hipStream_t st) {
   const TX* x = static_cast<const TX*>(X);
   T* y = static_cast<T*>(Y);
   const int xvec = ((reinterpret_cast<uintptr_t>(X) % 16) == 0 && (ldx * (int64_t)sizeof(TX)) % 16 == 0);
-  const int avec = ((m.p * (int64_t)sizeof(T)) % 16) == 0;  // A rows start 16-byte aligned
-  switch ((m.r + 15) / 16) {
-    case 1: launch_af_rb<TX, T, 1>(x, n, ldx, m.p, A, b, m.r, y, ldy, xvec, avec, st); break;
-    case 2: launch_af_rb<TX, T, 2>(x, n, ldx, m.p, A, b, m.r, y, ldy, xvec, avec, st); break;
-    case 3: launch_af_rb<TX, T, 3>(x, n, ldx, m.p, A, b, m.r, y, ldy, xvec, avec, st); break;
-    default: launch_af_rb<TX, T, 4>(x, n, ldx, m.p, A, b, m.r, y, ldy, xvec, avec, st); break;
+  const int avec = ((reinterpret_cast<uintptr_t>(A) % 16) == 0 && (p * (int64_t)sizeof(T)) % 16 == 0);
+  switch ((r + 15) / 16) {
+    case 1: launch_af_rb<TX, T, 1>(x, n, ldx, p, A, b, r, y, ldy, xvec, avec, st); break;
+    case 2: launch_af_rb<TX, T, 2>(x, n, ldx, p, A, b, r, y, ldy, xvec, avec, st); break;
+    case 3: launch_af_rb<TX, T, 3>(x, n, ldx, p, A, b, r, y, ldy, xvec, avec, st); break;
+    default: launch_af_rb<TX, T, 4>(x, n, ldx, p, A, b, r, y, ldy, xvec, avec, st); break;
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
-mds_status launch_embed_affine(const Model& m, int prec64, const void* X, int dt, int64_t n,
-                               int64_t ldx, void* Y, int64_t ldy, hipStream_t st) {
+mds_status launch_affine_raw(const void* A, const void* b, int prec64, int64_t p, int r, const void* X,
+                             int dt, int64_t n, int64_t ldx, void* Y, int64_t ldy, hipStream_t st) {
   hipError_t e;
-  if (prec64)
-    e = (dt == MDS_F64) ? launch_af<double, double>(m, X, n, ldx, Y, ldy, st)
-                        : launch_af<float, double>(m, X, n, ldx, Y, ldy, st);
-  else
-    e = launch_af<float, float>(m, X, n, ldx, Y, ldy, st);
+  if (prec64) {
+    const double* a = static_cast<const double*>(A);
+    const double* bb = static_cast<const double*>(b);
+    e = (dt == MDS_F64) ? launch_af<double, double>(a, bb, p, r, X, n, ldx, Y, ldy, st)
+                        : launch_af<float, double>(a, bb, p, r, X, n, ldx, Y, ldy, st);
+  } else {
+    e = launch_af<float, float>(static_cast<const float*>(A), static_cast<const float*>(b), p, r, X, n,
+                                ldx, Y, ldy, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "affine embed");
   return MDS_OK;
+}
+
+mds_status launch_embed_affine(const Model& m, int prec64, const void* X, int dt, int64_t n,
+                               int64_t ldx, void* Y, int64_t ldy, hipStream_t st) {
+  return launch_affine_raw(prec64 ? m.aff64 : m.aff32, prec64 ? m.affb64 : m.affb32, prec64, m.p, m.r,
+                           X, dt, n, ldx, Y, ldy, st);
 }
 
 }  // namespace mds

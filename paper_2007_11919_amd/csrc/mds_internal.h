@@ -124,6 +124,20 @@ mds_status dc_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx
 // double Y, else FP32 arithmetic and float Y (X float).
 mds_status launch_embed_affine(const Model& m, int prec64, const void* X, int dt, int64_t n,
                                int64_t ldx, void* Y, int64_t ldy, hipStream_t st);
+// the same for an affine map given by device pointers (A: r x p, b: r)
+mds_status launch_affine_raw(const void* A, const void* b, int prec64, int64_t p, int r, const void* X,
+                             int dt, int64_t n, int64_t ldx, void* Y, int64_t ldy, hipStream_t st);
+// top-r eigenpairs of the symmetric d x d FP64 matrix G (device, destroyed):
+// lam (device, r, descending; zero beyond d), U (device, d x r row-major),
+// status[0] = 1 when lambda_1 <= 0 (dc.hip)
+mds_status dense_top_eigen(double* G, int d, int r, double* lam, double* U, int* status,
+                           hipStream_t st);
+// MaxMin landmarks and pivot MDS (pivot.hip); arguments validated by the API
+mds_status maxmin_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
+                            int64_t first, int64_t* idx_host, hipStream_t st);
+mds_status pivot_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int r,
+                           const int64_t* idx_host, double* Y, int64_t ldy, double* lam_host,
+                           int32_t* r_eff, hipStream_t st);
 mds_status launch_embed_sqdist(const Model& m, int prec64, const void* A2, int dt, int64_t n,
                                int64_t lda, void* Y, int64_t ldy, hipStream_t st);
 // persistent serving launch over a device table of tiles

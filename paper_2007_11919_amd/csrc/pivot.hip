@@ -1,0 +1,474 @@
+// MaxMin landmark selection and pivot MDS (Section 3.1), FP64.
+//
+// MaxMin (the landmark choice of LMDS): from a given first point, add the
+// point whose smallest squared distance to the chosen points is largest.
+// Each step is one pass over X: a block stages 256 rows x 32 columns
+// through LDS with coalesced loads; thread t sums (x - m)^2 over its row's
+// columns in order, with a separately rounded product and sum per column
+// (so the values do not depend on how rows are grouped), keeps the running
+// minimum, and the block reports its largest minimum (smallest row on
+// ties).  A one-block kernel merges the block results in order and appends
+// the next landmark; the steps run back to back on the stream.
+//
+// Pivot MDS: C is the double-centred n x l block of squared distances
+// between all points and the pivots, and its singular value decomposition
+// C = U Sigma W' stands in for the eigendecomposition of Q; Q's eigenvalues
+// are estimated as lambda = sigma sqrt(n / l) and the configuration is
+// U_r Lambda_r^{1/2}; direction k is live when sigma_k^2 > TAU sigma_1^2.
+// For squared Euclidean distances the double-centred
+// block is C = Xc Mc' (Xc: rows minus their mean, Mc: pivots minus their
+// mean), so C'C = Mc S Mc' with S = Xc'Xc (p x p), and
+//     U_r Lambda_r^{1/2} = Xc Mc' W_r diag(lambda^{1/2} / sigma),
+// an affine map of the rows.  The work is one pass for the means, one for
+// S, an l x l symmetric eigenproblem, and one streaming pass for Y.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mds_internal.h"
+
+namespace mds {
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  hipStream_t st = nullptr;
+  ~Buf() {
+    if (p) (void)hipFreeAsync(p, st);
+  }
+  template <typename T>
+  T* get() const {
+    return static_cast<T*>(p);
+  }
+};
+
+#define PV_HIP(call)                                     \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) return hip_fail(_e, #call);    \
+  } while (0)
+
+#define PV_LAUNCH(what)                                  \
+  do {                                                   \
+    hipError_t _e = hipGetLastError();                   \
+    if (_e != hipSuccess) return hip_fail(_e, what);     \
+  } while (0)
+
+constexpr int MM_ROWS = 256;
+constexpr int MM_COLS = 32;
+
+// ---------------------------------------------------------------- MaxMin
+// Step s: distances to landmark idx[s]; dmin <- min(dmin, d) (set on the
+// first step); per block the largest dmin and its smallest row.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_mm_step(const TX* __restrict__ X, int64_t ldx, int64_t n,
+                                                 int64_t p, const int64_t* __restrict__ idx, int s,
+                                                 double* __restrict__ dmin, double* __restrict__ bval,
+                                                 int64_t* __restrict__ bidx) {
+  __shared__ TX xs[MM_ROWS][MM_COLS + 1];
+  __shared__ double ms[MM_COLS];
+  __shared__ double wv[4];
+  __shared__ int64_t wi[4];
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * MM_ROWS;
+  const int nrows = (int)((n - row0) < MM_ROWS ? (n - row0) : MM_ROWS);
+  const TX* mrow = X + idx[s] * ldx;
+  double acc = 0.0;
+  for (int64_t c0 = 0; c0 < p; c0 += MM_COLS) {
+    const int nc = (int)((p - c0) < MM_COLS ? (p - c0) : MM_COLS);
+    for (int e = t; e < MM_ROWS * MM_COLS; e += 256) {
+      const int rr = e / MM_COLS, cc = e % MM_COLS;
+      xs[rr][cc] = (rr < nrows && cc < nc) ? X[(row0 + rr) * ldx + c0 + cc] : (TX)0;
+    }
+    if (t < MM_COLS) ms[t] = (t < nc) ? (double)mrow[c0 + t] : 0.0;
+    __syncthreads();
+    for (int cc = 0; cc < nc; ++cc) {
+      const double d = (double)xs[t][cc] - ms[cc];
+      acc = __dadd_rn(acc, __dmul_rn(d, d));
+    }
+    __syncthreads();
+  }
+  double best = -1.0;
+  int64_t at = INT64_MAX;
+  if (t < nrows) {
+    const int64_t i = row0 + t;
+    const double v = (s == 0) ? acc : fmin(dmin[i], acc);
+    dmin[i] = v;
+    best = v;
+    at = i;
+  }
+  // largest value, smallest row on ties: a total order, so any merge order
+  // gives the same result
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(best, off, 64);
+    const int64_t oi = __shfl_xor(at, off, 64);
+    if (ov > best || (ov == best && oi < at)) {
+      best = ov;
+      at = oi;
+    }
+  }
+  if ((t & 63) == 0) {
+    wv[t >> 6] = best;
+    wi[t >> 6] = at;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (wv[w] > best || (wv[w] == best && wi[w] < at)) {
+        best = wv[w];
+        at = wi[w];
+      }
+    bval[blockIdx.x] = best;
+    bidx[blockIdx.x] = at;
+  }
+}
+
+// merge the block results of step s - 1 into landmark s; flag[0] = 1 when
+// the largest smallest distance is zero (fewer than l distinct points)
+__global__ __launch_bounds__(256) void k_mm_pick(const double* __restrict__ bval,
+                                                 const int64_t* __restrict__ bidx, int nb,
+                                                 int64_t* __restrict__ idx, int s,
+                                                 int* __restrict__ flag) {
+  __shared__ double wv[4];
+  __shared__ int64_t wi[4];
+  const int t = threadIdx.x;
+  double best = -1.0;
+  int64_t at = INT64_MAX;
+  for (int b = t; b < nb; b += 256) {
+    const double v = bval[b];
+    const int64_t i = bidx[b];
+    if (v > best || (v == best && i < at)) {
+      best = v;
+      at = i;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(best, off, 64);
+    const int64_t oi = __shfl_xor(at, off, 64);
+    if (ov > best || (ov == best && oi < at)) {
+      best = ov;
+      at = oi;
+    }
+  }
+  if ((t & 63) == 0) {
+    wv[t >> 6] = best;
+    wi[t >> 6] = at;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (wv[w] > best || (wv[w] == best && wi[w] < at)) {
+        best = wv[w];
+        at = wi[w];
+      }
+    if (!(best > 0.0)) {
+      flag[0] = 1;
+      at = idx[s - 1];  // keep a valid row; the host reports the error
+    }
+    idx[s] = at;
+  }
+}
+
+// ---------------------------------------------------------- pivot MDS
+// Column sums of rows [c * rows_per, (c + 1) * rows_per), in row order.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_colsum_part(const TX* __restrict__ X, int64_t ldx, int64_t n,
+                                                     int64_t p, int64_t rows_per,
+                                                     double* __restrict__ part, int* __restrict__ bad) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (k >= p) return;
+  const int64_t i0 = c * rows_per, i1 = std::min(n, i0 + rows_per);
+  double acc = 0.0;
+  bool fin = true;
+  for (int64_t i = i0; i < i1; ++i) {
+    const double v = (double)X[i * ldx + k];
+    fin = fin && isfinite(v);
+    acc += v;
+  }
+  part[c * p + k] = acc;
+  if (!fin) bad[0] = 1;
+}
+
+// out[k] = scale * sum over c of part[c][k], in order of c
+__global__ void k_sum_parts(const double* __restrict__ part, int64_t nparts, int64_t len, double scale,
+                            double* __restrict__ out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double acc = 0.0;
+  for (int64_t c = 0; c < nparts; ++c) acc += part[c * len + k];
+  out[k] = acc * scale;
+}
+
+// Partial S over rows [c * rows_per, (c + 1) * rows_per): 64x64 tile per
+// block, 4x4 per thread, rows staged 16 at a time, centred on the mean.
+// S[a][b] and S[b][a] are the same sums of the same products.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_cov_part(const TX* __restrict__ X, int64_t ldx, int64_t n,
+                                                  int64_t p, const double* __restrict__ mean,
+                                                  int64_t rows_per, double* __restrict__ part) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  const int64_t a0 = (int64_t)blockIdx.y * 64, b0 = (int64_t)blockIdx.x * 64;
+  const int64_t c = blockIdx.z;
+  const int64_t i0 = c * rows_per, i1 = std::min(n, i0 + rows_per);
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int64_t s0 = i0; s0 < i1; s0 += 16) {
+    for (int e = t; e < 16 * 64; e += 256) {
+      const int ii = e >> 6, cc = e & 63;
+      const int64_t i = s0 + ii;
+      double va = 0.0, vb = 0.0;
+      if (i < i1) {
+        const TX* row = X + i * ldx;
+        if (a0 + cc < p) va = (double)row[a0 + cc] - mean[a0 + cc];
+        if (b0 + cc < p) vb = (double)row[b0 + cc] - mean[b0 + cc];
+      }
+      As[ii][cc] = va;
+      Bs[ii][cc] = vb;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = As[kk][ty + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][tx + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  double* Sp = part + c * p * p;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t a = a0 + ty + 16 * u, b = b0 + tx + 16 * v;
+      if (a < p && b < p) Sp[a * p + b] = acc[u][v];
+    }
+}
+
+// Mc[j][k] = X[idx[j]][k] - mbar[k]; mbar = mean of the pivot rows (one
+// thread per column, pivots in the given order).
+template <typename TX>
+__global__ void k_pivots_centred(const TX* __restrict__ X, int64_t ldx, int64_t p,
+                                 const int64_t* __restrict__ idx, int64_t l, double* __restrict__ Mc) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= p) return;
+  double acc = 0.0;
+  for (int64_t j = 0; j < l; ++j) acc += (double)X[idx[j] * ldx + k];
+  const double mb = acc / (double)l;
+  for (int64_t j = 0; j < l; ++j) Mc[j * p + k] = (double)X[idx[j] * ldx + k] - mb;
+}
+
+// T = Mc S (l x p), one output per thread
+__global__ void k_mc_s(const double* __restrict__ Mc, const double* __restrict__ S, int64_t l,
+                       int64_t p, double* __restrict__ T) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= l * p) return;
+  const int64_t j = e / p, k = e % p;
+  double acc = 0.0;
+  for (int64_t q = 0; q < p; ++q) acc = fma(Mc[j * p + q], S[q * p + k], acc);
+  T[e] = acc;
+}
+
+// K = T Mc' (l x l), then symmetrised: K[i][j] = (K[i][j] + K[j][i]) / 2,
+// computed identically for both entries
+__global__ void k_t_mct(const double* __restrict__ T, const double* __restrict__ Mc, int64_t l,
+                        int64_t p, double* __restrict__ K) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= l * l) return;
+  const int64_t i = e / l, j = e % l;
+  double a = 0.0, b = 0.0;
+  for (int64_t q = 0; q < p; ++q) {
+    a = fma(T[i * p + q], Mc[j * p + q], a);
+    b = fma(T[j * p + q], Mc[i * p + q], b);
+  }
+  K[e] = (i <= j) ? 0.5 * (a + b) : 0.5 * (b + a);
+}
+
+// A[t][k] = fac[t] * sum_j Mc[j][k] W[j][t] (r x p); b[t] = -sum_k A[t][k] xbar[k]
+__global__ void k_pivot_affine(const double* __restrict__ Mc, const double* __restrict__ W, int64_t l,
+                               int64_t p, int r, const double* __restrict__ fac,
+                               double* __restrict__ A) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)r * p) return;
+  const int64_t t = e / p, k = e % p;
+  double acc = 0.0;
+  for (int64_t j = 0; j < l; ++j) acc = fma(Mc[j * p + k], W[j * r + t], acc);
+  A[e] = fac[t] * acc;
+}
+
+__global__ void k_affine_shift(const double* __restrict__ A, const double* __restrict__ xbar, int64_t p,
+                               int r, double* __restrict__ b) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r) return;
+  double acc = 0.0;
+  for (int64_t k = 0; k < p; ++k) acc = fma(A[(int64_t)t * p + k], xbar[k], acc);
+  b[t] = -acc;
+}
+
+template <typename TX>
+mds_status maxmin_run(const TX* X, int64_t ldx, int64_t n, int64_t p, int64_t l, int64_t first,
+                      int64_t* idx_host, hipStream_t st) {
+  const int nb = (int)((n + MM_ROWS - 1) / MM_ROWS);
+  Buf dmin, bval, bidx, idx, flag;
+  auto alloc = [&](Buf& b, size_t bytes) -> hipError_t {
+    b.st = st;
+    return hipMallocAsync(&b.p, std::max<size_t>(bytes, 256), st);
+  };
+  PV_HIP(alloc(dmin, sizeof(double) * n));
+  PV_HIP(alloc(bval, sizeof(double) * nb));
+  PV_HIP(alloc(bidx, sizeof(int64_t) * nb));
+  PV_HIP(alloc(idx, sizeof(int64_t) * l));
+  PV_HIP(alloc(flag, sizeof(int)));
+  PV_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  PV_HIP(hipMemcpyAsync(idx.p, &first, sizeof(int64_t), hipMemcpyHostToDevice, st));
+  for (int s = 0; s + 1 < l; ++s) {
+    k_mm_step<TX><<<nb, 256, 0, st>>>(X, ldx, n, p, idx.get<int64_t>(), s, dmin.get<double>(),
+                                      bval.get<double>(), bidx.get<int64_t>());
+    k_mm_pick<<<1, 256, 0, st>>>(bval.get<double>(), bidx.get<int64_t>(), nb, idx.get<int64_t>(), s + 1,
+                                 flag.get<int>());
+  }
+  PV_LAUNCH("maxmin steps");
+  int hflag = 0;
+  PV_HIP(hipMemcpyAsync(idx_host, idx.p, sizeof(int64_t) * l, hipMemcpyDeviceToHost, st));
+  PV_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  PV_HIP(hipStreamSynchronize(st));
+  if (hflag) return set_error(MDS_ERR_DEGENERATE, "fewer than l distinct points");
+  return MDS_OK;
+}
+
+template <typename TX>
+mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int64_t l, int r,
+                     const int64_t* idx_host, double* Y, int64_t ldy, double* lam_host, int32_t* r_eff,
+                     hipStream_t st) {
+  // row chunks: enough blocks to fill the device, partial S within ~512 MB
+  const int64_t by_mem = std::max<int64_t>(1, ((int64_t)512 << 20) / (int64_t)(sizeof(double) * p * p));
+  const int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>({(n + 1023) / 1024, 1024, by_mem}));
+  const int64_t rows_per = (n + nchunks - 1) / nchunks;
+  Buf idx, part, xbar, Spart, S, Mc, T, K, lam, W, stat, fac, A, b, bad;
+  auto alloc = [&](Buf& bb, size_t bytes) -> hipError_t {
+    bb.st = st;
+    return hipMallocAsync(&bb.p, std::max<size_t>(bytes, 256), st);
+  };
+  PV_HIP(alloc(idx, sizeof(int64_t) * l));
+  PV_HIP(alloc(part, sizeof(double) * nchunks * p));
+  PV_HIP(alloc(xbar, sizeof(double) * p));
+  PV_HIP(alloc(Spart, sizeof(double) * nchunks * p * p));
+  PV_HIP(alloc(S, sizeof(double) * p * p));
+  PV_HIP(alloc(Mc, sizeof(double) * l * p));
+  PV_HIP(alloc(T, sizeof(double) * l * p));
+  PV_HIP(alloc(K, sizeof(double) * l * l));
+  PV_HIP(alloc(lam, sizeof(double) * r));
+  PV_HIP(alloc(W, sizeof(double) * l * r));
+  PV_HIP(alloc(stat, sizeof(int)));
+  PV_HIP(alloc(fac, sizeof(double) * r));
+  PV_HIP(alloc(A, sizeof(double) * r * p));
+  PV_HIP(alloc(b, sizeof(double) * r));
+  PV_HIP(alloc(bad, sizeof(int)));
+  PV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+  PV_HIP(hipMemcpyAsync(idx.p, idx_host, sizeof(int64_t) * l, hipMemcpyHostToDevice, st));
+  {
+    dim3 g((unsigned)((p + 255) / 256), (unsigned)nchunks);
+    k_colsum_part<TX><<<g, 256, 0, st>>>(X, ldx, n, p, rows_per, part.get<double>(), bad.get<int>());
+    k_sum_parts<<<(unsigned)((p + 255) / 256), 256, 0, st>>>(part.get<double>(), nchunks, p,
+                                                            1.0 / (double)n, xbar.get<double>());
+    const unsigned tiles = (unsigned)((p + 63) / 64);
+    dim3 gc(tiles, tiles, (unsigned)nchunks);
+    k_cov_part<TX><<<gc, 256, 0, st>>>(X, ldx, n, p, xbar.get<double>(), rows_per, Spart.get<double>());
+    k_sum_parts<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(Spart.get<double>(), nchunks, p * p, 1.0,
+                                                                S.get<double>());
+    k_pivots_centred<TX><<<(unsigned)((p + 255) / 256), 256, 0, st>>>(X, ldx, p, idx.get<int64_t>(), l,
+                                                                     Mc.get<double>());
+    k_mc_s<<<(unsigned)((l * p + 255) / 256), 256, 0, st>>>(Mc.get<double>(), S.get<double>(), l, p,
+                                                           T.get<double>());
+    k_t_mct<<<(unsigned)((l * l + 255) / 256), 256, 0, st>>>(T.get<double>(), Mc.get<double>(), l, p,
+                                                            K.get<double>());
+    PV_LAUNCH("pivot Gram matrices");
+  }
+  mds_status s = dense_top_eigen(K.get<double>(), (int)l, r, lam.get<double>(), W.get<double>(),
+                                 stat.get<int>(), st);
+  if (s != MDS_OK) return s;
+  std::vector<double> th(r), hw((size_t)l * r);
+  int hstat = 0, hbad = 0;
+  PV_HIP(hipMemcpyAsync(th.data(), lam.p, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+  PV_HIP(hipMemcpyAsync(hw.data(), W.p, sizeof(double) * l * r, hipMemcpyDeviceToHost, st));
+  PV_HIP(hipMemcpyAsync(&hstat, stat.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  PV_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  PV_HIP(hipStreamSynchronize(st));
+  if (hbad) return set_error(MDS_ERR_INVALID_ARG, "non-finite value in X");
+  if (hstat) return set_error(MDS_ERR_DEGENERATE, "largest eigenvalue is not positive");
+  // sigma^2 = eigenvalues of C'C; lambda = sigma sqrt(n / l); column signs
+  // from W (largest-|.| entry positive, first on ties)
+  // a direction is live when sigma^2 > TAU sigma_1^2 (the eigenvalue test
+  // on C'C itself); dead directions report lambda = 0
+  std::vector<double> hfac(r, 0.0);
+  int live = 0;
+  for (int t = 0; t < r; ++t) {
+    const double sigma = std::sqrt(std::max(th[t], 0.0));
+    const double lamt = sigma * std::sqrt((double)n / (double)l);
+    const bool is_live = th[t] > MDS_TAU * th[0];
+    if (lam_host) lam_host[t] = is_live ? lamt : 0.0;
+    if (!is_live) continue;
+    ++live;
+    double best = -1.0, val = 0.0;
+    for (int64_t j = 0; j < l; ++j) {
+      const double v = hw[(size_t)j * r + t];
+      if (std::fabs(v) > best) {
+        best = std::fabs(v);
+        val = v;
+      }
+    }
+    hfac[t] = (val < 0.0 ? -1.0 : 1.0) * std::sqrt(lamt) / sigma;
+  }
+  if (r_eff) *r_eff = live;
+  PV_HIP(hipMemcpyAsync(fac.p, hfac.data(), sizeof(double) * r, hipMemcpyHostToDevice, st));
+  k_pivot_affine<<<(unsigned)((r * p + 255) / 256), 256, 0, st>>>(Mc.get<double>(), W.get<double>(), l, p,
+                                                                 r, fac.get<double>(), A.get<double>());
+  k_affine_shift<<<1, 64, 0, st>>>(A.get<double>(), xbar.get<double>(), p, r, b.get<double>());
+  PV_LAUNCH("pivot affine map");
+  s = launch_affine_raw(A.p, b.p, 1, p, r, X, dt, n, ldx, Y, ldy, st);
+  if (s != MDS_OK) return s;
+  PV_HIP(hipStreamSynchronize(st));
+  return MDS_OK;
+}
+
+}  // namespace
+
+mds_status maxmin_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
+                            int64_t first, int64_t* idx_host, hipStream_t st) {
+  if (l == 1) {
+    idx_host[0] = first;
+    return MDS_OK;
+  }
+  if (dt == MDS_F32)
+    return maxmin_run<float>(static_cast<const float*>(X), ldx, n, p, l, first, idx_host, st);
+  return maxmin_run<double>(static_cast<const double*>(X), ldx, n, p, l, first, idx_host, st);
+}
+
+mds_status pivot_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int r,
+                           const int64_t* idx_host, double* Y, int64_t ldy, double* lam_host,
+                           int32_t* r_eff, hipStream_t st) {
+  if (dt == MDS_F32)
+    return pivot_run<float>(static_cast<const float*>(X), dt, ldx, n, p, l, r, idx_host, Y, ldy, lam_host,
+                            r_eff, st);
+  return pivot_run<double>(static_cast<const double*>(X), dt, ldx, n, p, l, r, idx_host, Y, ldy, lam_host,
+                           r_eff, st);
+}
+
+}  // namespace mds

@@ -1,0 +1,114 @@
+"""MaxMin landmarks and pivot MDS through the C ABI against the FP64 oracle
+(needs a GPU): MaxMin indices must match exactly, pivot MDS to FP64
+tolerances."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pivot as opv
+from synth import errors
+from synth import generators as gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_Y = 1e-9
+TOL_LAM = 1e-12
+
+
+def mds():
+    import paper_2007_11919_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("name,make,l,first", [
+    ("gaussian", lambda: gen.small_gaussian(5000, seed=1), 50, 0),
+    ("ragged n, fp32", lambda: gen.wide_gaussian(3001, seed=2), 40, 17),
+    ("integer image rows", lambda: gen.image_mixture(2000, p=784, seed=3).astype(np.float64), 30, 5),
+    ("one landmark", lambda: gen.small_gaussian(100, seed=4), 1, 9),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_maxmin_matches_oracle(name, make, l, first):
+    X = make()
+    idx = mds().maxmin_landmarks(dev(X), l, first)
+    ref = opv.maxmin_landmarks(X.astype(np.float64), l, first)
+    assert np.array_equal(idx, ref), (idx[:10], ref[:10])
+
+
+def test_maxmin_strided_and_duplicates():
+    X = gen.small_gaussian(700, seed=5)
+    wide = np.zeros((700, 13))
+    wide[:, :10] = X
+    idx = mds().maxmin_landmarks(dev(wide)[:, :10], 25, 3)
+    assert np.array_equal(idx, opv.maxmin_landmarks(X, 25, 3))
+    D = np.zeros((50, 3))
+    D[7] = 1.0
+    with pytest.raises(mds().MDSError) as ei:
+        mds().maxmin_landmarks(dev(D), 3, 0)
+    assert ei.value.status == 4
+
+
+def compare_pivot(X, l, r, seed=0, idx=None, dtype=np.float64):
+    Xs = X.astype(dtype)
+    Y, lam, r_eff = mds().pivot_mds(dev(Xs), l, r, seed=seed, idx=idx)
+    pidx = np.asarray(idx) if idx is not None else np.array(oracle.sample_landmarks(X.shape[0], l, seed))
+    Yo, lamo, _ = opv.pivot_mds(Xs.astype(np.float64), pidx, r)
+    assert np.max(np.abs(lam - lamo)) <= TOL_LAM * lamo[0], (lam, lamo)
+    e = errors.column_errors(Y.cpu().numpy(), Yo)
+    assert e["maxabs_rms"] <= TOL_Y, e
+    assert r_eff == int(np.sum(lamo > oracle.TAU * lamo[0]))
+    return Y.cpu().numpy(), lam
+
+
+@pytest.mark.parametrize("name,make,l,r", [
+    ("paper design, l=200", lambda: gen.paper_design(20000, 10, 2, seed=6), 200, 2),
+    ("wide, eigen in LDS", lambda: gen.wide_gaussian(8000, seed=7).astype(np.float64), 80, 10),
+    ("wide, eigen in global memory", lambda: gen.wide_gaussian(8000, seed=8).astype(np.float64), 300, 10),
+    ("rank below r", lambda: gen.small_gaussian(2000, seed=9)[:, :3], 50, 5),
+    ("all rows are pivots", lambda: gen.small_gaussian(150, seed=10), 150, 3),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_pivot_matches_oracle(name, make, l, r):
+    X = make()
+    Y, _ = compare_pivot(X, l, r, seed=3)
+    if name == "rank below r":
+        assert np.all(Y[:, 3:] == 0.0)
+
+
+def test_pivot_with_maxmin_pivots_and_fp32():
+    X = gen.wide_gaussian(6000, seed=11)
+    idx = mds().maxmin_landmarks(dev(X), 120, 0)
+    compare_pivot(X, 120, 10, idx=idx, dtype=np.float32)
+
+
+def test_pivot_full_size_sampled_rows():
+    """n = 10^6 rows of the 100-column workload, l = 200 random pivots (the
+    pivot MDS setting of Section 4.1), r = 10; rows sampled for the check."""
+    X = gen.wide_gaussian(1_000_000, seed=12)
+    Y, lam, _ = mds().pivot_mds(dev(X), 200, 10, seed=4)
+    pidx = np.array(oracle.sample_landmarks(1_000_000, 200, 4))
+    rows = np.sort(np.random.default_rng(0).choice(1_000_000, 3000, replace=False))
+    Yo, lamo, _ = opv.pivot_mds_large(X, pidx, 10, rows=rows)
+    assert np.max(np.abs(lam - lamo)) <= 1e-10 * lamo[0], (lam, lamo)
+    e = errors.column_errors(Y.cpu().numpy()[rows], Yo)
+    assert e["maxabs_rms"] <= 1e-8, e
+
+
+def test_pivot_error_codes():
+    m = mds()
+    X = dev(gen.small_gaussian(300, seed=13))
+    for l, r in [(1, 1), (50, 50), (301, 2), (3000, 2)]:
+        with pytest.raises(m.MDSError) as ei:
+            m.pivot_mds(X, l, r)
+        assert ei.value.status == 1, (l, r)
+    with pytest.raises(m.MDSError) as ei:
+        m.pivot_mds(X, 10, 2, idx=np.array([1, 2, 3, 4, 5, 6, 7, 8, 9, 9]))
+    assert ei.value.status == 1
+    bad = gen.small_gaussian(300, seed=13)
+    bad[5, 1] = np.inf
+    with pytest.raises(m.MDSError) as ei:
+        m.pivot_mds(dev(bad), 20, 2)
+    assert ei.value.status == 1

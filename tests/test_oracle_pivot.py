@@ -165,3 +165,14 @@ def test_planted_mistake_in_scale(monkeypatch):
     monkeypatch.setattr(opv, "pivot_mds", no_scale)
     with pytest.raises(AssertionError):
         test_paper_design_statistics()
+
+
+def test_large_route_matches_direct():
+    X = gen.small_gaussian(3000, seed=21)[:, :6]
+    idx = np.array(oracle.sample_landmarks(3000, 60, 2))
+    Y, lam, W = opv.pivot_mds(X, idx, 3)
+    rows = np.array([0, 5, 1000, 2999])
+    Yl, laml, Wl = opv.pivot_mds_large(X, idx, 3, rows=rows, chunk=700)
+    assert pins._rel(laml, lam) < 1e-12
+    assert pins._rel(Wl, W) < 1e-9
+    assert pins._rel(Yl, Y[rows]) < 1e-9
