@@ -295,6 +295,54 @@ def affine_leg(mds, torch, model, Xd, Y64, iters):
             "note": "separate mode (affine form of eq. (2)); not the distance-block path"}
 
 
+def pivot_leg(mds, torch, Xd, X, iters, cpu):
+    """MaxMin selection of l = 200 landmarks (one pass over X per landmark)
+    and pivot MDS with l = 200 random pivots, r = 10 (Section 4.1's pivot
+    MDS setting), on the 10^6 x 100 rows."""
+    from synth import errors
+    import oracle
+    from oracle import pivot as opv
+    n, p = Xd.shape
+    l, r = 200, 10
+    st = torch.cuda.current_stream()
+    mds.maxmin_landmarks(Xd, 8, 0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    mm = mds.maxmin_landmarks(Xd, l, 0)
+    t_mm = time.perf_counter() - t
+    mm_bytes = (l - 1) * (4.0 * n * p + 16.0 * n)
+    Y, lam, r_eff = mds.pivot_mds(Xd, l, r, seed=4)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(iters):
+        mds.pivot_mds(Xd, l, r, seed=4, Y=Y)
+    t_pv = (time.perf_counter() - t) / iters
+    out = {"maxmin": {"l": l, "ms": t_mm * 1e3, "ms_per_landmark": t_mm * 1e3 / (l - 1),
+                      "roofline": {"bound": "hbm", "achieved": mm_bytes / t_mm / 1e9,
+                                   "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                   "frac": mm_bytes / t_mm / PEAK_HBM,
+                                   "bytes": mm_bytes}},
+           "pivot_mds": {"l": l, "r": r, "pivots": "random", "ms": t_pv * 1e3,
+                         "points_per_s": n / t_pv, "lam_over_n": [float(v) / n for v in lam],
+                         "r_eff": r_eff}}
+    pidx = np.array(oracle.sample_landmarks(n, l, 4))
+    rows = np.sort(np.random.default_rng(0).choice(n, 3000, replace=False))
+    t = time.perf_counter()
+    Yo, lamo, _ = opv.pivot_mds_large(X, pidx, r, rows=rows)
+    t_orc = time.perf_counter() - t
+    e = errors.column_errors(Y.cpu().numpy()[rows], Yo)
+    out["pivot_mds"]["err_vs_oracle_rows"] = {"rows": len(rows),
+                                              **{k: e[k] for k in ("rms_rel", "maxabs_rms")}}
+    if cpu:
+        out["pivot_mds"]["cpu_baseline"] = {
+            "value": n / t_orc, "unit": "points/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
+            "sample": f"oracle (chunked FP64 expansion, all {n} rows for C'C, {len(rows)} rows "
+                      f"output) {t_orc:.1f} s, counted as a whole pass (output of the other rows "
+                      f"not included)"}
+    return out
+
+
 DC = dict(n=1_000_000, k=100, h=10, l=400, c=50, r=10,
           desc="divide-and-conquer MDS, 1,000,000 x 100 rows of the simulation design "
                "(10 columns of variance 15, 90 of variance 1), l=400, c=5r=50, r=10; "
@@ -413,6 +461,7 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0)
     ap.add_argument("--no-dc", action="store_true")
     ap.add_argument("--no-affine", action="store_true")
+    ap.add_argument("--no-pivot", action="store_true")
     ap.add_argument("--dc-iters", type=int, default=5)
     ap.add_argument("--only-dc", action="store_true", help="run --iters divide-and-conquer calls only")
     args = ap.parse_args()
@@ -541,6 +590,9 @@ def main():
     if not args.no_affine:
         log("affine form")
         out["embed_affine"] = affine_leg(mds, torch, model, Xd, Y64n, args.embed_iters)
+    if args.workload == "wide" and not args.no_pivot:
+        log("maxmin and pivot MDS")
+        out["maxmin_pivot"] = pivot_leg(mds, torch, Xd, X, args.dc_iters, not args.no_cpu_baseline)
     if args.workload == "wide" and not args.no_dc:
         log("divide-and-conquer MDS")
         out["divide_conquer"] = dc_leg(mds, torch, args.dc_iters, not args.no_cpu_baseline)

@@ -76,15 +76,30 @@ __global__ __launch_bounds__(256) void k_mm_step(const TX* __restrict__ X, int64
   const int64_t row0 = (int64_t)blockIdx.x * MM_ROWS;
   const int nrows = (int)((n - row0) < MM_ROWS ? (n - row0) : MM_ROWS);
   const TX* mrow = X + idx[s] * ldx;
+  // thread t stages column t % 32, rows t / 32 + 8 u, of each 256 x 32
+  // chunk; the next chunk is loaded into registers while the current one is
+  // summed
+  constexpr int PER = MM_ROWS * MM_COLS / 256;
+  constexpr int RSTEP = 256 / MM_COLS;
+  const int cc0 = t % MM_COLS, rb = t / MM_COLS;
+  const TX* xbase = X + (row0 + rb) * ldx + cc0;
+  const int64_t rstride = (int64_t)RSTEP * ldx;
+  TX reg[PER];
+  auto load = [&](int64_t c0) {
+    const bool cin = c0 + cc0 < p;
+    const TX* src = xbase + c0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) reg[u] = (cin && rb + RSTEP * u < nrows) ? src[u * rstride] : (TX)0;
+  };
   double acc = 0.0;
+  load(0);
   for (int64_t c0 = 0; c0 < p; c0 += MM_COLS) {
     const int nc = (int)((p - c0) < MM_COLS ? (p - c0) : MM_COLS);
-    for (int e = t; e < MM_ROWS * MM_COLS; e += 256) {
-      const int rr = e / MM_COLS, cc = e % MM_COLS;
-      xs[rr][cc] = (rr < nrows && cc < nc) ? X[(row0 + rr) * ldx + c0 + cc] : (TX)0;
-    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) xs[rb + RSTEP * u][cc0] = reg[u];
     if (t < MM_COLS) ms[t] = (t < nc) ? (double)mrow[c0 + t] : 0.0;
     __syncthreads();
+    if (c0 + MM_COLS < p) load(c0 + MM_COLS);
     for (int cc = 0; cc < nc; ++cc) {
       const double d = (double)xs[t][cc] - ms[cc];
       acc = __dadd_rn(acc, __dmul_rn(d, d));
@@ -175,33 +190,53 @@ __global__ __launch_bounds__(256) void k_mm_pick(const double* __restrict__ bval
 }
 
 // ---------------------------------------------------------- pivot MDS
-// Column sums of rows [c * rows_per, (c + 1) * rows_per), in row order.
+// Column sums of rows [c * rows_per, (c + 1) * rows_per): a block covers 64
+// columns of one chunk, its four waves take the rows i = w (mod 4), and the
+// four partials are added in order.
 template <typename TX>
 __global__ __launch_bounds__(256) void k_colsum_part(const TX* __restrict__ X, int64_t ldx, int64_t n,
                                                      int64_t p, int64_t rows_per,
                                                      double* __restrict__ part, int* __restrict__ bad) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double ws[4][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
   const int64_t c = blockIdx.y;
-  if (k >= p) return;
   const int64_t i0 = c * rows_per, i1 = std::min(n, i0 + rows_per);
   double acc = 0.0;
   bool fin = true;
-  for (int64_t i = i0; i < i1; ++i) {
-    const double v = (double)X[i * ldx + k];
-    fin = fin && isfinite(v);
-    acc += v;
-  }
-  part[c * p + k] = acc;
+  if (k < p)
+    for (int64_t i = i0 + g; i < i1; i += 4) {
+      const double v = (double)X[i * ldx + k];
+      fin = fin && isfinite(v);
+      acc += v;
+    }
+  ws[g][lane] = acc;
   if (!fin) bad[0] = 1;
+  __syncthreads();
+  if (g == 0 && k < p) part[c * p + k] = ((ws[0][lane] + ws[1][lane]) + ws[2][lane]) + ws[3][lane];
 }
 
-// out[k] = scale * sum over c of part[c][k], in order of c
-__global__ void k_sum_parts(const double* __restrict__ part, int64_t nparts, int64_t len, double scale,
+// out[k] = scale * sum over c of part[c][k]: the chunks are split into
+// PSEG segments summed in parallel, then the segments in order.
+constexpr int PSEG = 16;
+__global__ void k_sum_seg(const double* __restrict__ part, int64_t nparts, int64_t len,
+                          double* __restrict__ seg) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int sg = blockIdx.y;
+  if (k >= len) return;
+  const int64_t per = (nparts + PSEG - 1) / PSEG;
+  const int64_t c0 = sg * per, c1 = std::min(nparts, c0 + per);
+  double acc = 0.0;
+  for (int64_t c = c0; c < c1; ++c) acc += part[c * len + k];
+  seg[sg * len + k] = acc;
+}
+
+__global__ void k_sum_parts(const double* __restrict__ seg, int64_t len, double scale,
                             double* __restrict__ out) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= len) return;
   double acc = 0.0;
-  for (int64_t c = 0; c < nparts; ++c) acc += part[c * len + k];
+  for (int sg = 0; sg < PSEG; ++sg) acc += seg[sg * len + k];
   out[k] = acc * scale;
 }
 
@@ -361,7 +396,7 @@ mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int
   const int64_t by_mem = std::max<int64_t>(1, ((int64_t)512 << 20) / (int64_t)(sizeof(double) * p * p));
   const int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>({(n + 1023) / 1024, 1024, by_mem}));
   const int64_t rows_per = (n + nchunks - 1) / nchunks;
-  Buf idx, part, xbar, Spart, S, Mc, T, K, lam, W, stat, fac, A, b, bad;
+  Buf idx, part, xbar, Spart, S, Mc, T, K, lam, W, stat, fac, A, b, bad, seg;
   auto alloc = [&](Buf& bb, size_t bytes) -> hipError_t {
     bb.st = st;
     return hipMallocAsync(&bb.p, std::max<size_t>(bytes, 256), st);
@@ -371,6 +406,7 @@ mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int
   PV_HIP(alloc(xbar, sizeof(double) * p));
   PV_HIP(alloc(Spart, sizeof(double) * nchunks * p * p));
   PV_HIP(alloc(S, sizeof(double) * p * p));
+  PV_HIP(alloc(seg, sizeof(double) * PSEG * p * p));
   PV_HIP(alloc(Mc, sizeof(double) * l * p));
   PV_HIP(alloc(T, sizeof(double) * l * p));
   PV_HIP(alloc(K, sizeof(double) * l * l));
@@ -384,14 +420,18 @@ mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int
   PV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
   PV_HIP(hipMemcpyAsync(idx.p, idx_host, sizeof(int64_t) * l, hipMemcpyHostToDevice, st));
   {
-    dim3 g((unsigned)((p + 255) / 256), (unsigned)nchunks);
+    dim3 g((unsigned)((p + 63) / 64), (unsigned)nchunks);
     k_colsum_part<TX><<<g, 256, 0, st>>>(X, ldx, n, p, rows_per, part.get<double>(), bad.get<int>());
-    k_sum_parts<<<(unsigned)((p + 255) / 256), 256, 0, st>>>(part.get<double>(), nchunks, p,
-                                                            1.0 / (double)n, xbar.get<double>());
+    dim3 gs((unsigned)((p + 255) / 256), PSEG);
+    k_sum_seg<<<gs, 256, 0, st>>>(part.get<double>(), nchunks, p, seg.get<double>());
+    k_sum_parts<<<(unsigned)((p + 255) / 256), 256, 0, st>>>(seg.get<double>(), p, 1.0 / (double)n,
+                                                            xbar.get<double>());
     const unsigned tiles = (unsigned)((p + 63) / 64);
     dim3 gc(tiles, tiles, (unsigned)nchunks);
     k_cov_part<TX><<<gc, 256, 0, st>>>(X, ldx, n, p, xbar.get<double>(), rows_per, Spart.get<double>());
-    k_sum_parts<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(Spart.get<double>(), nchunks, p * p, 1.0,
+    dim3 gs2((unsigned)((p * p + 255) / 256), PSEG);
+    k_sum_seg<<<gs2, 256, 0, st>>>(Spart.get<double>(), nchunks, p * p, seg.get<double>());
+    k_sum_parts<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(seg.get<double>(), p * p, 1.0,
                                                                 S.get<double>());
     k_pivots_centred<TX><<<(unsigned)((p + 255) / 256), 256, 0, st>>>(X, ldx, p, idx.get<int64_t>(), l,
                                                                      Mc.get<double>());
