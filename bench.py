@@ -9,11 +9,17 @@ Default workload: 1,000,000 x 100 Gaussian rows (first 10 std devs 20 -> 2,
 then 1), l = 1000 landmarks, r = 10.  Also reported on the same data:
 the split-BF16 embed (speed-up and error), the embed kernel's roofline
 fraction, serving latency (p50/p99) at three loads, and the FP64 oracle on
-the host cores (bounded sample).
+the host cores (bounded sample).  Further legs, each with its own roofline
+and error check: the embed from squared dissimilarities (Section 2 input),
+the affine form of eq. (2), MaxMin landmark selection and pivot MDS
+(Section 3.1), and divide-and-conquer MDS (Section 3.2) on the simulation
+design of Section 4.1.
 
     python bench.py [--steps K] [--warmup W] [--workload wide|image]
     python bench.py --only-embed fp32 --iters 20     (for rocprofv3 runs)
     python bench.py --only-fit --iters 5              (for rocprofv3 runs)
+    python bench.py --only-dc | --only-affine | --only-sqdist | --only-pivot --iters K
+                                                      (the other kernels, for rocprofv3 runs)
     python bench.py --copy-calib 1073741824           (counter calibration)
 """
 
@@ -464,6 +470,11 @@ def main():
     ap.add_argument("--no-pivot", action="store_true")
     ap.add_argument("--dc-iters", type=int, default=5)
     ap.add_argument("--only-dc", action="store_true", help="run --iters divide-and-conquer calls only")
+    ap.add_argument("--only-affine", action="store_true", help="run --iters affine embeds only")
+    ap.add_argument("--only-sqdist", action="store_true",
+                    help="run --iters embeds from squared dissimilarities only")
+    ap.add_argument("--only-pivot", action="store_true",
+                    help="run one MaxMin selection and --iters pivot MDS calls only")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -508,6 +519,36 @@ def main():
             mds.fit_landmarks(Xd, w["l"], w["r"], seed=0).free()
         torch.cuda.synchronize()
         print(json.dumps({"only_fit": args.iters}))
+        return
+
+    if args.only_affine or args.only_sqdist:
+        model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
+        if args.only_affine:
+            Y = mds.embed_affine(model, Xd, prec="fp32")
+            for _ in range(args.iters):
+                mds.embed_affine(model, Xd, prec="fp32", Y=Y)
+        else:
+            idx = torch.from_numpy(model.landmarks()).to(dev)
+            M = Xd[idx]
+            A2 = torch.empty((w["n"], w["l"]), dtype=torch.float32, device=dev)
+            mn = (M * M).sum(1)
+            for s0 in range(0, w["n"], 100_000):
+                xb = Xd[s0:s0 + 100_000]
+                A2[s0:s0 + 100_000] = ((xb * xb).sum(1, keepdim=True) + mn[None, :]
+                                       - 2.0 * (xb @ M.T)).clamp_min_(0)
+            Y = mds.embed_from_sqdist(model, A2, prec="fp32")
+            for _ in range(args.iters):
+                mds.embed_from_sqdist(model, A2, prec="fp32", Y=Y)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "affine" if args.only_affine else "sqdist", "iters": args.iters}))
+        return
+
+    if args.only_pivot:
+        mds.maxmin_landmarks(Xd, 200, 0)
+        for _ in range(args.iters):
+            mds.pivot_mds(Xd, 200, 10, seed=4)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "pivot", "iters": args.iters}))
         return
 
     if args.only_embed:
