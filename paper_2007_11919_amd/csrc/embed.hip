@@ -429,6 +429,561 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
   __syncthreads();
 }
 
+// ---- split precisions at large p: 512 landmarks per pass over the row tile
+// With p in the hundreds a 128-row tile of X is too large to stay in L2
+// while the block walks the landmarks, so every landmark tile re-reads (and
+// re-splits) it from memory.  This variant keeps the 128-row tile but
+// walks the landmarks WBN = 512 at a time: eight waves as 2 row halves x 4
+// landmark quarters, each 64 rows x 128 landmarks of accumulators, so X is
+// read and split a quarter as often.  One chunk buffer (X hi/lo 16 KB +
+// landmarks 64 KB) is double-buffered, which fills the 160 KB of LDS;
+// 16-byte segments are XOR-swizzled by row instead of padded, and the
+// landmark operands are copied from memory straight into LDS (the split
+// packs are allocated to a multiple of WBN rows, zero past l_pad).  The row
+// norms pass once through the buffer just consumed.  The quarters are
+// added in order at the end.  The landmark order of the sums differs from
+// the 128-landmark variant, so each model and precision always runs the
+// same variant (plain and serving launches alike).
+constexpr int WBN = 512;
+constexpr int WTHREADS = 512;
+constexpr int WX_BYTES = BM * CHUNK_BYTES;
+constexpr int WBUF_BYTES = WX_BYTES + WBN * CHUNK_BYTES;
+constexpr int WLDS_BYTES = 2 * WBUF_BYTES;
+static_assert(WBN == kSplitPackRows, "split packs are padded for this variant");
+
+// s_waitcnt immediate for vmcnt(0) with the other counters left alone
+constexpr int kWaitVm0 = 0x0F70;
+
+// byte offset of 16-byte segment seg (0..7) in a 128-byte row of LDS
+__device__ inline int swz(int row, int seg) { return (seg ^ (row & 7)) << 4; }
+
+template <int MODE>
+__device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restrict__ X, int64_t ldx,
+                                int nrows, float* __restrict__ Y, int64_t ldy, char* lds) {
+  using V = typename std::conditional<MODE == MODE_BF16, bf8, h8>::type;
+  constexpr int E = 4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1;   // 64-row half
+  const int wn = wave >> 1;  // 128-landmark quarter
+  const int lr = lane & 15;
+  const int lg = lane >> 4;
+  const int p = mv.p;
+  const int nch = mv.nchunks;
+  const int64_t l_pad = (int64_t)mv.ntl * BN;
+  const int nst = (int)((l_pad + WBN - 1) / WBN);
+  const int total = nch * nst;
+  const bool xvec = ((((uintptr_t)X) & 15) == 0) && ((ldx * (int64_t)sizeof(float)) % 16 == 0);
+  const bool xfast = xvec && (p % E == 0);
+  const bool do_mlo = !mv.m_lo_zero;
+
+  // loader mapping: X rows lrow + 64 u (u < 2), 16-byte slot lseg
+  const int lrow = tid >> 3;
+  const int lseg = tid & 7;
+
+  f4 acc[8][4];  // [landmark block][row block]
+  f4 yacc[4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+#pragma unroll
+  for (int b = 0; b < 4; ++b) yacc[b] = f4{0, 0, 0, 0};
+  float nacc[2] = {0.f, 0.f};
+  float xn[4] = {0.f, 0.f, 0.f, 0.f};
+  Seg<float, E> xr[2];
+
+  // Landmark operands go from memory straight into LDS (16 bytes per lane,
+  // no registers): wave load u of wave w fills the 1 KB of landmark rows
+  // 64 u + 8 w .. + 8, lane L the physical segment L % 8 of row L / 8, so
+  // it fetches the logical segment (L % 8) ^ (row % 8).
+  const int64_t mrow_bytes = (int64_t)nch * CHUNK_BYTES;
+  const char* mlane = reinterpret_cast<const char*>(mv.mpack) +
+                      (int64_t)(8 * wave + (lane >> 3)) * mrow_bytes + (((lane & 7) ^ (lane >> 3)) << 4);
+  auto dma_chunk = [&](int s, int ch, int buf) {
+    char* mb = lds + buf * WBUF_BYTES + WX_BYTES + 8 * wave * CHUNK_BYTES;
+    const char* src = mlane + (int64_t)s * WBN * mrow_bytes + (int64_t)ch * CHUNK_BYTES;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + (int64_t)(64 * u) * mrow_bytes),
+                                       (__attribute__((address_space(3))) void*)(mb + 64 * u * CHUNK_BYTES),
+                                       16, 0, 0);
+  };
+
+  // data rows: pointer to the lane's 16-byte slot of row lrow + 64 u (the
+  // last row stands in for rows past nrows, whose values are zeroed)
+  const float* xrow[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int row = lrow + 64 * u;
+    xrow[u] = X + (int64_t)(row < nrows ? row : nrows - 1) * ldx + lseg * E;
+  }
+  auto load_chunk = [&](int ch) {
+    const int64_t k0 = (int64_t)ch * 32 + lseg * E;
+    if (xfast) {
+      const bool kin = k0 < p;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool in = kin && (lrow + 64 * u < nrows);
+        const u4 raw = *reinterpret_cast<const u4*>(xrow[u] + (kin ? (int64_t)ch * 32 : 0));
+        const u4 z = {0u, 0u, 0u, 0u};
+        const u4 v = in ? raw : z;
+        __builtin_memcpy(&xr[u], &v, 16);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int row = lrow + 64 * u;
+        if (row < nrows) {
+          xr[u] = load_seg<float, E>(X + (int64_t)row * ldx, k0, p, xvec);
+        } else {
+#pragma unroll
+          for (int i = 0; i < E; ++i) xr[u].v[i] = 0.f;
+        }
+      }
+    }
+  };
+  auto accumulate_norm = [&]() {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int i = 0; i < E; ++i) nacc[u] = fma(xr[u].v[i], xr[u].v[i], nacc[u]);
+  };
+  auto store_chunk = [&](int buf) {
+    char* xb = lds + buf * WBUF_BYTES;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int row = lrow + 64 * u;
+      uint16_t hi[4], lo[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float x = xr[u].v[i];
+        if constexpr (MODE == MODE_BF16) {
+          const __bf16 h = (__bf16)x;
+          const __bf16 lw = (__bf16)(x - (float)h);
+          hi[i] = __builtin_bit_cast(uint16_t, h);
+          lo[i] = __builtin_bit_cast(uint16_t, lw);
+        } else {
+          x *= mv.prescale;
+          const _Float16 h = (_Float16)x;
+          const _Float16 lw = (_Float16)(x - (float)h);
+          hi[i] = __builtin_bit_cast(uint16_t, h);
+          lo[i] = __builtin_bit_cast(uint16_t, lw);
+        }
+      }
+      const u2 hv = {(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
+      const u2 lv = {(uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
+      // the 8 hi bytes of elements 4 lseg.. sit in hi segment lseg / 2
+      char* rowp = xb + row * CHUNK_BYTES + (lseg & 1) * 8;
+      *reinterpret_cast<u2*>(rowp + swz(row, lseg >> 1)) = hv;
+      *reinterpret_cast<u2*>(rowp + swz(row, 4 + (lseg >> 1))) = lv;
+    }
+  };
+  // The products with the data lo parts are skipped when every lo part the
+  // wave holds is zero (integer-valued data): they would add exact zeros.
+  auto compute_chunk = [&](int buf) {
+    const char* xb = lds + buf * WBUF_BYTES;
+    const char* mb = xb + WX_BYTES;
+    V bh[4], bl[4];
+    bool lo_nz = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 64 * wm + 16 * j + lr;
+      bh[j] = *reinterpret_cast<const V*>(xb + row * CHUNK_BYTES + swz(row, lg));
+      bl[j] = *reinterpret_cast<const V*>(xb + row * CHUNK_BYTES + swz(row, 4 + lg));
+      const u4 bits = __builtin_bit_cast(u4, bl[j]);
+      lo_nz |= (bits[0] | bits[1] | bits[2] | bits[3]) != 0u;
+    }
+    const bool do_xlo = __builtin_amdgcn_ballot_w64(lo_nz) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int lm = 128 * wn + 16 * i + lr;
+      const V ah = *reinterpret_cast<const V*>(mb + lm * CHUNK_BYTES + swz(lm, lg));
+      V al;
+      if (do_mlo) al = *reinterpret_cast<const V*>(mb + lm * CHUNK_BYTES + swz(lm, 4 + lg));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if constexpr (MODE == MODE_BF16) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+          if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+          if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+        } else {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
+          if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
+          if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // e = c - |x|^2 + 2 s and Y^T += W^T E^T for the wave's quarter of super tile s
+  const float* cl = reinterpret_cast<const float*>(mv.c) + 128 * wn + 4 * lg;
+  const float* wl = reinterpret_cast<const float*>(mv.w) + (int64_t)lr * mv.ldwt + 128 * wn + 4 * lg;
+  auto epilogue = [&](int s) {
+    const float two = 2.0f * mv.postscale;
+    const float* cb = cl + (int64_t)s * WBN;
+    const float* wb = wl + (int64_t)s * WBN;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const f4 c4 = *reinterpret_cast<const f4*>(cb + 16 * i);
+      const f4 w4 = *reinterpret_cast<const f4*>(wb + 16 * i);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        f4 e;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) e[v] = (c4[v] - xn[j]) + two * acc[i][j][v];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) yacc[j] = mfma(w4[v], e[v], yacc[j]);
+        acc[i][j] = f4{0, 0, 0, 0};
+      }
+    }
+  };
+
+  // ---- pipeline over (super tile, chunk) ----
+  // The landmark copies of a chunk are waited for (vmcnt) before the
+  // barrier that publishes the chunk.
+  dma_chunk(0, 0, 0);
+  load_chunk(0);
+  accumulate_norm();
+  store_chunk(0);
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+  int s = 0, ch = 0;
+  for (int it = 0; it < total; ++it) {
+    const int buf = it & 1;
+    const bool has_next = it + 1 < total;
+    const int nchn = (ch + 1 == nch) ? 0 : ch + 1;
+    const int nsn = (ch + 1 == nch) ? s + 1 : s;
+    // a quarter wholly past the padded landmark count does no work
+    const bool live = (int64_t)s * WBN + 128 * wn < l_pad;
+    if (has_next) {
+      dma_chunk(nsn, nchn, buf ^ 1);
+      load_chunk(nchn);
+    }
+    if (live) compute_chunk(buf);
+    if (has_next) {
+      if (nsn == 0) accumulate_norm();
+      store_chunk(buf ^ 1);
+    }
+    const bool tile_end = (ch == nch - 1);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    if (tile_end) {
+      if (s == 0) {
+        // row norms (8 lanes per row, fixed butterfly) through buffer buf,
+        // which nobody reads or writes again before the next store into it
+        float* xnorm = reinterpret_cast<float*>(lds + buf * WBUF_BYTES);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          float t = nacc[u];
+          t += __shfl_xor(t, 4, 64);
+          t += __shfl_xor(t, 2, 64);
+          t += __shfl_xor(t, 1, 64);
+          if (lseg == 0) xnorm[lrow + 64 * u] = t;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xn[j] = xnorm[64 * wm + 16 * j + lr];
+        __syncthreads();
+      }
+      if (live) epilogue(s);
+    }
+    s = nsn;
+    ch = nchn;
+  }
+
+  // ---- add the four landmark quarters in order and store ----
+  __syncthreads();
+  float* ysh = reinterpret_cast<float*>(lds);
+  if (wn > 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ysh[((((wn - 1) * 2 + wm) * 4 + j) * 4 + v) * 64 + lane] = yacc[j][v];
+  }
+  __syncthreads();
+  if (wn == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 64 * wm + 16 * j + lr;
+      if (row >= nrows) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 4 * lg + v;
+        float val = yacc[j][v];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) val += ysh[(((q * 2 + wm) * 4 + j) * 4 + v) * 64 + lane];
+        if (col < mv.r) Y[(int64_t)row * ldy + col] = val;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// ---- the same at large p when every landmark lo part is zero ----
+// (integer-valued landmarks, the usual case for image data).  The landmark
+// operands are then hi parts only, 32 KB per 512 x 32 chunk, which leaves
+// room for three chunk buffers (X FP32 16 KB + landmarks 32 KB each), so the
+// copies run two chunks ahead of the MFMAs: data rows and landmarks both go
+// from memory straight into LDS, and each wave splits its own data
+// fragments into hi/lo after reading them (the four landmark quarters of a
+// row half split the same values, identically).  Barriers are raw s_barrier
+// with an explicit wait that leaves the newest chunk's copies in flight; a
+// compiler memory barrier keeps LDS accesses on their side of it.  The row
+// norms are summed by the consuming lanes themselves (8 columns each, then
+// a butterfly over the four lane groups).
+constexpr int WH_X = BM * CHUNK_BYTES;  // 128 rows x 32 FP32
+constexpr int WH_ROW = 64;              // landmark hi part of one chunk
+constexpr int WH_BUF = WH_X + WBN * WH_ROW;
+constexpr int WH_NBUF = 3;
+static_assert(WH_NBUF * WH_BUF <= WLDS_BYTES, "three buffers fit the LDS of the wide variant");
+// s_waitcnt immediates: lgkmcnt(0) with vmcnt(n)
+constexpr int kWaitLgkVm(int n) { return 0x0070 | n; }
+constexpr int kWhCopiesFast = 6;  // copies per chunk and wave: 2 data + 4 landmark
+constexpr int kWhCopiesSlow = 4;  // landmark copies only (data rows via registers)
+
+__device__ inline void raw_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::: "memory");
+}
+
+template <int MODE>
+__device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restrict__ X, int64_t ldx,
+                                  int nrows, float* __restrict__ Y, int64_t ldy, char* lds) {
+  using V = typename std::conditional<MODE == MODE_BF16, bf8, h8>::type;
+  constexpr int E = 4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1;   // 64-row half
+  const int wn = wave >> 1;  // 128-landmark quarter
+  const int lr = lane & 15;
+  const int lg = lane >> 4;
+  const int p = mv.p;
+  const int nch = mv.nchunks;
+  const int64_t l_pad = (int64_t)mv.ntl * BN;
+  const int nst = (int)((l_pad + WBN - 1) / WBN);
+  const int total = nch * nst;
+  const bool xvec = ((((uintptr_t)X) & 15) == 0) && ((ldx * (int64_t)sizeof(float)) % 16 == 0);
+  const bool xfast = xvec && (p % E == 0);
+  const int copies = xfast ? kWhCopiesFast : kWhCopiesSlow;
+
+  f4 acc[8][4];  // [landmark block][row block]
+  f4 yacc[4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+#pragma unroll
+  for (int b = 0; b < 4; ++b) yacc[b] = f4{0, 0, 0, 0};
+  float nacc[4] = {0.f, 0.f, 0.f, 0.f};
+  float xn[4] = {0.f, 0.f, 0.f, 0.f};
+
+  // data copies (fast path): wave copy u fills rows 64 u + 8 w .. + 8, lane
+  // L the physical segment L % 8 of row L / 8 (logical (L % 8) ^ (row % 8));
+  // rows past nrows repeat the last row and columns past p re-read the
+  // row's first columns (both finite, masked or discarded later)
+  const int xsub = lane >> 3;
+  const int xseg = (lane & 7) ^ xsub;
+  const float* xsrc[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int row = 64 * u + 8 * wave + xsub;
+    xsrc[u] = X + (int64_t)(row < nrows ? row : nrows - 1) * ldx + xseg * E;
+  }
+  // landmark copies: wave copy u fills landmark rows 128 u + 16 w .. + 16
+  // (64 bytes each), lane L the physical segment L % 4 of row L / 4
+  // (logical (L % 4) ^ (row % 4)); the hi half of each packed chunk
+  const int64_t mrow_bytes = (int64_t)nch * CHUNK_BYTES;
+  const char* mlane = reinterpret_cast<const char*>(mv.mpack) +
+                      (int64_t)(16 * wave + (lane >> 2)) * mrow_bytes + (((lane & 3) ^ ((lane >> 2) & 3)) << 4);
+  // slow path: register loads of 16-byte segments, zero outside the data
+  const int lrow = tid >> 3;
+  const int lseg = tid & 7;
+
+  auto issue = [&](int it, int b) {
+    const int s = it / nch, ch = it - (it / nch) * nch;
+    char* xb = lds + b * WH_BUF;
+    char* mb = xb + WH_X;
+    if (xfast) {
+      const int64_t koff = ((int64_t)ch * 32 + xseg * E < p) ? (int64_t)ch * 32 : 0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(xsrc[u] + koff),
+                                         (__attribute__((address_space(3))) void*)(xb + (64 * u + 8 * wave) * CHUNK_BYTES),
+                                         16, 0, 0);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int row = lrow + 64 * u;
+        Seg<float, E> v;
+        if (row < nrows) {
+          v = load_seg<float, E>(X + (int64_t)row * ldx, (int64_t)ch * 32 + lseg * E, p, xvec);
+        } else {
+#pragma unroll
+          for (int i = 0; i < E; ++i) v.v[i] = 0.f;
+        }
+        *reinterpret_cast<Seg<float, E>*>(xb + row * CHUNK_BYTES + swz(row, lseg)) = v;
+      }
+    }
+    const char* msrc = mlane + (int64_t)s * WBN * mrow_bytes + (int64_t)ch * CHUNK_BYTES;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(msrc + (int64_t)(128 * u) * mrow_bytes),
+                                       (__attribute__((address_space(3))) void*)(mb + (128 * u + 16 * wave) * WH_ROW),
+                                       16, 0, 0);
+  };
+
+  // The products with the data lo parts are skipped when every lo part the
+  // wave holds is zero: they would add exact zeros.
+  auto compute_chunk = [&](int b, int ch, bool norms) {
+    const char* xb = lds + b * WH_BUF;
+    const char* mb = xb + WH_X;
+    const int kbase = ch * 32 + 8 * lg;
+    const bool ktail = ch * 32 + 32 > p;
+    V bh[4], bl[4];
+    bool lo_nz = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 64 * wm + 16 * j + lr;
+      const f4 x0 = *reinterpret_cast<const f4*>(xb + row * CHUNK_BYTES + swz(row, 2 * lg));
+      const f4 x1 = *reinterpret_cast<const f4*>(xb + row * CHUNK_BYTES + swz(row, 2 * lg + 1));
+      float xv[8] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+      if (ktail) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xv[e] = (kbase + e < p) ? xv[e] : 0.f;
+      }
+      if (norms) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) nacc[j] = fma(xv[e], xv[e], nacc[j]);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if constexpr (MODE == MODE_BF16) {
+          const __bf16 h = (__bf16)xv[e];
+          const __bf16 lw = (__bf16)(xv[e] - (float)h);
+          bh[j][e] = h;
+          bl[j][e] = lw;
+          lo_nz |= ((float)lw != 0.0f);
+        } else {
+          const float x = xv[e] * mv.prescale;
+          const _Float16 h = (_Float16)x;
+          const _Float16 lw = (_Float16)(x - (float)h);
+          bh[j][e] = h;
+          bl[j][e] = lw;
+          lo_nz |= ((float)lw != 0.0f);
+        }
+      }
+    }
+    const bool do_xlo = __builtin_amdgcn_ballot_w64(lo_nz) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int lm = 128 * wn + 16 * i + lr;
+      const V ah = *reinterpret_cast<const V*>(mb + lm * WH_ROW + ((lg ^ (lm & 3)) << 4));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if constexpr (MODE == MODE_BF16) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+          if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+        } else {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
+          if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+  };
+  const float* cl = reinterpret_cast<const float*>(mv.c) + 128 * wn + 4 * lg;
+  const float* wl = reinterpret_cast<const float*>(mv.w) + (int64_t)lr * mv.ldwt + 128 * wn + 4 * lg;
+  auto epilogue = [&](int s) {
+    const float two = 2.0f * mv.postscale;
+    const float* cb = cl + (int64_t)s * WBN;
+    const float* wb = wl + (int64_t)s * WBN;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const f4 c4 = *reinterpret_cast<const f4*>(cb + 16 * i);
+      const f4 w4 = *reinterpret_cast<const f4*>(wb + 16 * i);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        f4 e;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) e[v] = (c4[v] - xn[j]) + two * acc[i][j][v];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) yacc[j] = mfma(w4[v], e[v], yacc[j]);
+        acc[i][j] = f4{0, 0, 0, 0};
+      }
+    }
+  };
+
+  // ---- pipeline: chunk it in buffer it % 3, copies two chunks ahead ----
+  issue(0, 0);
+  if (total > 1) {
+    issue(1, 1);
+    if (xfast) __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesFast));
+    else __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesSlow));
+  } else {
+    __builtin_amdgcn_s_waitcnt(kWaitLgkVm(0));
+  }
+  raw_barrier();
+  int b = 0;
+  for (int it = 0; it < total; ++it) {
+    const int s = it / nch, ch = it - (it / nch) * nch;
+    const bool live = (int64_t)s * WBN + 128 * wn < l_pad;
+    const bool ahead = it + 2 < total;
+    if (ahead) issue(it + 2, b == 0 ? 2 : b - 1);
+    if (live) compute_chunk(b, ch, s == 0);
+    const bool tile_end = (ch == nch - 1);
+    if (tile_end && s == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float t = nacc[j];
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        xn[j] = t;
+      }
+    }
+    // chunk it + 1 must have landed; the copies of chunk it + 2 may fly on
+    if (ahead) {
+      if (copies == kWhCopiesFast) __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesFast));
+      else __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesSlow));
+    } else {
+      __builtin_amdgcn_s_waitcnt(kWaitLgkVm(0));
+    }
+    raw_barrier();
+    if (tile_end && live) epilogue(s);
+    b = (b == 2) ? 0 : b + 1;
+  }
+
+  // ---- add the four landmark quarters in order and store ----
+  __syncthreads();
+  float* ysh = reinterpret_cast<float*>(lds);
+  if (wn > 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ysh[((((wn - 1) * 2 + wm) * 4 + j) * 4 + v) * 64 + lane] = yacc[j][v];
+  }
+  __syncthreads();
+  if (wn == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 64 * wm + 16 * j + lr;
+      if (row >= nrows) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 4 * lg + v;
+        float val = yacc[j][v];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) val += ysh[(((q * 2 + wm) * 4 + j) * 4 + v) * 64 + lane];
+        if (col < mv.r) Y[(int64_t)row * ldy + col] = val;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Two waves per SIMD (two blocks per CU) where the registers fit without
 // spilling; the FP64 and wide-output variants keep one.
 template <int MODE, int RB>
@@ -471,6 +1026,46 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(waves_p
   }
 }
 
+// HI: the landmark lo parts are all zero (three-stage form)
+template <int MODE, bool HI>
+__device__ inline void embed_tile_wide_v(const EmbedModelView& mv, const float* __restrict__ X,
+                                         int64_t ldx, int nrows, float* __restrict__ Y, int64_t ldy,
+                                         char* lds) {
+  if constexpr (HI)
+    embed_tile_wide_h<MODE>(mv, X, ldx, nrows, Y, ldy, lds);
+  else
+    embed_tile_wide<MODE>(mv, X, ldx, nrows, Y, ldy, lds);
+}
+
+template <int MODE, bool HI>
+__global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_wide(
+    EmbedModelView mv, const float* __restrict__ X, int64_t n, int64_t ldx, float* __restrict__ Y,
+    int64_t ldy) {
+  extern __shared__ __align__(16) char lds[];
+  const int64_t ntiles = (n + BM - 1) / BM;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * BM;
+    const int nrows = (int)((n - row0) < BM ? (n - row0) : BM);
+    embed_tile_wide_v<MODE, HI>(mv, X + row0 * ldx, ldx, nrows, Y + row0 * ldy, ldy, lds);
+  }
+}
+
+// serving form of the same variants (one tile table entry per 128 rows)
+template <int MODE, bool HI>
+__global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_work_wide(
+    const EmbedModelView* __restrict__ views, const TileWork* __restrict__ work,
+    const int32_t* __restrict__ nwork) {
+  extern __shared__ __align__(16) char lds[];
+  const int nw = nwork[0];
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+    const TileWork tw = work[w];
+    const EmbedModelView mv = views[tw.model];
+    const float* X = reinterpret_cast<const float*>(tw.x) + tw.row0 * tw.ldx;
+    float* Y = reinterpret_cast<float*>(tw.y) + tw.row0 * tw.ldy;
+    embed_tile_wide_v<MODE, HI>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+  }
+}
+
 int g_num_cu = 0;
 
 int num_cu() {
@@ -500,6 +1095,31 @@ hipError_t launch_t(const EmbedModelView& mv, const void* X, int64_t n, int64_t 
   k_embed<MODE, TX, RB><<<grid, THREADS, LDS_BYTES, st>>>(mv, reinterpret_cast<const TX*>(X), n, ldx,
                                                            Y, ldy);
   return hipGetLastError();
+}
+
+template <int MODE, bool HI>
+hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
+                         int64_t ldy, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed_wide<MODE, HI>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, WLDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int64_t ntiles = (n + BM - 1) / BM;
+  const int64_t cap = (int64_t)num_cu() * 64;
+  const int grid = (int)(ntiles < cap ? ntiles : cap);
+  k_embed_wide<MODE, HI><<<grid, WTHREADS, WLDS_BYTES, st>>>(mv, reinterpret_cast<const float*>(X), n,
+                                                             ldx, reinterpret_cast<float*>(Y), ldy);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_wide(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
+                       int64_t ldy, hipStream_t st) {
+  return mv.m_lo_zero ? launch_wide_v<MODE, true>(mv, X, n, ldx, Y, ldy, st)
+                      : launch_wide_v<MODE, false>(mv, X, n, ldx, Y, ldy, st);
 }
 
 template <int MODE, typename TX>
@@ -571,10 +1191,12 @@ mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t
       e = launch_rb<MODE_F32, float>(mv, X, n, ldx, Y, ldy, st);
       break;
     case MODE_BF16:
-      e = launch_rb<MODE_BF16, float>(mv, X, n, ldx, Y, ldy, st);
+      e = embed_wide(mode, m.p, m.rb) ? launch_wide<MODE_BF16>(mv, X, n, ldx, Y, ldy, st)
+                                      : launch_rb<MODE_BF16, float>(mv, X, n, ldx, Y, ldy, st);
       break;
     default:
-      e = launch_rb<MODE_F16, float>(mv, X, n, ldx, Y, ldy, st);
+      e = embed_wide(mode, m.p, m.rb) ? launch_wide<MODE_F16>(mv, X, n, ldx, Y, ldy, st)
+                                      : launch_rb<MODE_F16, float>(mv, X, n, ldx, Y, ldy, st);
       break;
   }
   if (e != hipSuccess) return hip_fail(e, "embed launch");
@@ -587,7 +1209,13 @@ const void* worklist_fn_rb(int rbc) {
   switch (rbc) {
     case 0: return reinterpret_cast<const void*>(&k_embed_work<MODE, 1>);
     case 1: return reinterpret_cast<const void*>(&k_embed_work<MODE, 2>);
-    default: return reinterpret_cast<const void*>(&k_embed_work<MODE, 4>);
+    case 2: return reinterpret_cast<const void*>(&k_embed_work<MODE, 4>);
+    case kWideClass:
+      if constexpr (MODE == MODE_F32) return nullptr;
+      else return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, false>);
+    default:
+      if constexpr (MODE == MODE_F32) return nullptr;
+      else return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, true>);
   }
 }
 const void* worklist_fn(int mode, int rbc) {
@@ -598,7 +1226,7 @@ const void* worklist_fn(int mode, int rbc) {
     default: return nullptr;
   }
 }
-bool g_work_attr[4][3] = {};
+bool g_work_attr[4][kEmbedClasses] = {};
 
 template <int MODE>
 void launch_work_rb(int rbc, int grid, hipStream_t st, const EmbedModelView* v, const TileWork* w,
@@ -606,15 +1234,28 @@ void launch_work_rb(int rbc, int grid, hipStream_t st, const EmbedModelView* v, 
   switch (rbc) {
     case 0: k_embed_work<MODE, 1><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
     case 1: k_embed_work<MODE, 2><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
-    default: k_embed_work<MODE, 4><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
+    case 2: k_embed_work<MODE, 4><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
+    case kWideClass:
+      if constexpr (MODE != MODE_F32)
+        k_embed_work_wide<MODE, false><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw);
+      break;
+    default:
+      if constexpr (MODE != MODE_F32)
+        k_embed_work_wide<MODE, true><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw);
+      break;
   }
 }
 }  // namespace
 
 int rb_class(int rb) { return rb <= 1 ? 0 : (rb == 2 ? 1 : 2); }
 
+int embed_class(int mode, int64_t p, int rb, int m_lo_zero) {
+  if (!embed_wide(mode, p, rb)) return rb_class(rb);
+  return m_lo_zero ? kWideHiClass : kWideClass;
+}
+
 int embed_blocks_per_cu(int mode, int rbc) {
-  if (mode == MODE_F64 || rbc == 2) return 1;
+  if (mode == MODE_F64 || rbc >= 2) return 1;
   if (rbc == 0) return 2;
   return mode == MODE_F32 ? 2 : 1;
 }
@@ -624,7 +1265,8 @@ mds_status prepare_embed_worklist(int mode, int rbc) {
   const void* fn = worklist_fn(mode, rbc);
   if (!fn) return set_error(MDS_ERR_INVALID_ARG, "serving supports FP32 and split precisions");
   if (!g_work_attr[mode][rbc]) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       rbc >= kWideClass ? WLDS_BYTES : LDS_BYTES);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
     g_work_attr[mode][rbc] = true;
   }

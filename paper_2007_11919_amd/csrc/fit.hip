@@ -429,36 +429,74 @@ __global__ __launch_bounds__(256) void k_bias(const double* __restrict__ M, int6
 // Affine form of eq. (2) for Euclidean input: y = A x + b with
 // A[k][i] = 2 sum_j W[j][k] M[j][i] and b[k] = sum_j W[j][k] c[j] (the
 // |x|^2 term drops out because the columns of V sum to zero).  Column i == p
-// of the grid computes b.  A block covers 64 columns of one output k; its
-// four waves take the landmarks j = w (mod 4), combined in order.
+// of the grid computes b.  Block (column block, landmark chunk z): its four
+// waves take the landmarks j = w (mod 4) of chunk z, each lane one column i
+// and 16 outputs k at a time; the wave partials are added in order and the
+// chunk partials are summed in order by k_affine_sum.
 __global__ __launch_bounds__(256) void k_affine_map(const double* __restrict__ M, int64_t ldm,
                                                     int64_t l, int64_t p,
                                                     const double* __restrict__ W, int ldw,
                                                     const double* __restrict__ c, int r,
-                                                    double* __restrict__ A64, float* __restrict__ A32,
-                                                    double* __restrict__ b64, float* __restrict__ b32) {
-  __shared__ double part[4][64];
+                                                    double* __restrict__ part) {
+  __shared__ double ws[4][16][64];
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int k = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-  double acc = 0.0;
-  if (i <= p) {
-    if (i < p)
-      for (int64_t j = g; j < l; j += 4) acc = fma(W[j * ldw + k], M[j * ldm + i], acc);
-    else
-      for (int64_t j = g; j < l; j += 4) acc = fma(W[j * ldw + k], c[j], acc);
-  }
-  part[g][lane] = acc;
-  __syncthreads();
-  if (g == 0 && i <= p) {
-    const double s = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-    if (i < p) {
-      A64[(int64_t)k * p + i] = 2.0 * s;
-      A32[(int64_t)k * p + i] = (float)(2.0 * s);
-    } else {
-      b64[k] = s;
-      b32[k] = (float)s;
+  const int64_t nz = gridDim.y;
+  const int64_t per = (l + nz - 1) / nz;
+  const int64_t j0 = blockIdx.y * per, j1 = (j0 + per < l) ? j0 + per : l;
+  for (int k0 = 0; k0 < r; k0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    if (i <= p) {
+      for (int64_t j = j0 + g; j < j1; j += 4) {
+        const double mv = (i < p) ? M[j * ldm + i] : c[j];
+        const double* wr = W + j * ldw + k0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (k0 + u < r) acc[u] = fma(wr[u], mv, acc[u]);
+      }
     }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) ws[g][u][lane] = acc[u];
+    __syncthreads();
+    if (g == 0 && i <= p) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        if (k0 + u >= r) break;
+        const double s = ((ws[0][u][lane] + ws[1][u][lane]) + ws[2][u][lane]) + ws[3][u][lane];
+        part[((int64_t)blockIdx.y * r + k0 + u) * (p + 1) + i] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// A = 2 x (sum of the chunk partials of columns i < p), b = sum for i == p
+__global__ void k_affine_sum(const double* __restrict__ part, int nz, int64_t p, int r,
+                             double* __restrict__ A64, float* __restrict__ A32,
+                             double* __restrict__ b64, float* __restrict__ b32) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)r * (p + 1)) return;
+  const int64_t k = e / (p + 1), i = e % (p + 1);
+  const int64_t zs = (int64_t)r * (p + 1);
+  const double* pp = part + k * (p + 1) + i;
+  double s = 0.0;
+  int z = 0;
+  for (; z + 8 <= nz; z += 8) {  // eight loads in flight, added in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = pp[(z + u) * zs];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; z < nz; ++z) s += pp[z * zs];
+  if (i < p) {
+    A64[k * p + i] = 2.0 * s;
+    A32[k * p + i] = (float)(2.0 * s);
+  } else {
+    b64[k] = s;
+    b32[k] = (float)s;
   }
 }
 
@@ -591,8 +629,10 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   Layout lay;
   const size_t o64 = lay.take(sizeof(double) * l_pad * ldm);
   const size_t o32 = lay.take(sizeof(float) * l_pad * nch32 * 32);
-  const size_t obf = lay.take(sizeof(uint16_t) * l_pad * nch32 * 64);
-  const size_t oh = lay.take(sizeof(uint16_t) * l_pad * nch32 * 64);
+  // split packs: rows up to a multiple of kSplitPackRows (zero past l_pad)
+  const int64_t l_split = round_up(l_pad, kSplitPackRows);
+  const size_t obf = lay.take(sizeof(uint16_t) * l_split * nch32 * 64);
+  const size_t oh = lay.take(sizeof(uint16_t) * l_split * nch32 * 64);
   const size_t ow32 = lay.take(sizeof(float) * l_pad * ldw);
   const size_t ow64 = lay.take(sizeof(double) * l_pad * ldw);
   const size_t oc32 = lay.take(sizeof(float) * l_pad);
@@ -844,10 +884,21 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     k_pack32<<<grid, 256, 0, st>>>((const double*)m.m64, ldm, l_pad, p, nch32, (float*)m.m32,
                                    (uint16_t*)m.mbf, (uint16_t*)m.mh, scales, ctrl + 4);
-    dim3 agrid((unsigned)((p + 1 + 63) / 64), (unsigned)r);
+    // landmark chunks for the affine map (each wave walks a few landmarks,
+    // so the loop is not a chain of memory latencies): up to 64, partials
+    // within 64 MB
+    const int64_t cols = (int64_t)r * (p + 1);
+    const int nz = (int)std::max<int64_t>(1, std::min<int64_t>({64, (l + 15) / 16,
+                                                                (int64_t)(8 << 20) / cols}));
+    DevBuf baff;
+    MDS_HIP(hipMallocAsync(&baff.p, sizeof(double) * (size_t)nz * cols, st));
+    baff.st = st;
+    dim3 agrid((unsigned)((p + 1 + 63) / 64), (unsigned)nz);
     k_affine_map<<<agrid, 256, 0, st>>>((const double*)m.m64, ldm, l, p, (const double*)m.w64, ldw,
-                                        (const double*)m.c64, r, (double*)m.aff64, (float*)m.aff32,
-                                        (double*)m.affb64, (float*)m.affb32);
+                                        (const double*)m.c64, r, (double*)baff.p);
+    k_affine_sum<<<(unsigned)((cols + 255) / 256), 256, 0, st>>>(
+        (const double*)baff.p, nz, p, r, (double*)m.aff64, (float*)m.aff32, (double*)m.affb64,
+        (float*)m.affb32);
   } else {
     k_scale<<<1, 256, 0, st>>>(rowmax, 0, scales);  // unused without vectors
   }

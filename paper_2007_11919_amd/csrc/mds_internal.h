@@ -27,6 +27,19 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 // elements of the contraction per chunk in each mode
 inline int chunk_elems(int mode) { return mode == MODE_F64 ? 16 : 32; }
 
+// Split-precision models with one 16-column output block and p >= kWideMinP
+// run the variant of the embed kernel that walks the landmarks 512 at a time
+// (plain and serving launches alike, so a row's result does not depend on
+// the launch it arrives in).
+constexpr int kWideMinP = 256;
+constexpr int kSplitPackRows = 512;  // split packs hold round_up(l_pad, this) rows
+constexpr int kEmbedClasses = 5;
+constexpr int kWideClass = 3;    // wide variant, landmark lo parts present
+constexpr int kWideHiClass = 4;  // wide variant, landmark lo parts all zero
+inline bool embed_wide(int mode, int64_t p, int rb) {
+  return (mode == MODE_BF16 || mode == MODE_F16) && rb == 1 && p >= kWideMinP;
+}
+
 // Device-side view of one model for one precision, passed by value.
 struct EmbedModelView {
   const void* mpack;   // l_pad rows x nchunks x CHUNK_BYTES landmark operands
@@ -141,12 +154,14 @@ mds_status pivot_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t 
 mds_status launch_embed_sqdist(const Model& m, int prec64, const void* A2, int dt, int64_t n,
                                int64_t lda, void* Y, int64_t ldy, hipStream_t st);
 // persistent serving launch over a device table of tiles
-// rbc = rb_class(rb): 0 for rb 1, 1 for rb 2, 2 for rb 3..4
+// rbc = embed_class(...): 0 for rb 1, 1 for rb 2, 2 for rb 3..4, and
+// kWideClass / kWideHiClass for the 512-landmark split-precision variants
 mds_status launch_embed_worklist(int mode, int rbc, const EmbedModelView* views_dev,
                                  const TileWork* work_dev, const int32_t* nwork_dev,
                                  int grid, hipStream_t st);
 int embed_max_rb();
 int rb_class(int rb);
+int embed_class(int mode, int64_t p, int rb, int m_lo_zero);
 int embed_blocks_per_cu(int mode, int rbc);
 mds_status prepare_embed_worklist(int mode, int rbc);
 

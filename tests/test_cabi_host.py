@@ -105,3 +105,32 @@ def test_serve_argument_errors_need_no_gpu(L):
     t = ctypes.c_int64()
     assert L.mds_serve_submit(None, 0, None, 0, 1, 1, None, 1, ctypes.byref(t)) == 1
     L.mds_serve_destroy(None)  # no-op
+
+
+def test_next_row_entry_points_reject_bad_arguments_without_gpu(L):
+    fake = ctypes.c_void_p(16)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    out = np.empty(8, dtype=np.int64)
+    lam = (ctypes.c_double * 4)()
+    reff = ctypes.c_int32(0)
+    # divide-and-conquer: c < r + 1, l <= c, n <= c, l too large, NULL X
+    for n, l, c, r in [(100, 20, 2, 2), (100, 10, 10, 2), (10, 20, 10, 2), (10**5, 4096, 50, 2)]:
+        assert L.mds_divide_conquer(fake, 0, n, 4, 4, l, c, r, 0, fake, r, lam, ctypes.byref(reff),
+                                    None, None) == 1, (n, l, c, r)
+    assert L.mds_divide_conquer(None, 0, 100, 4, 4, 20, 5, 2, 0, fake, 2, lam, None, None, None) == 1
+    # MaxMin: l > n, first out of range, NULL output
+    assert L.mds_maxmin_landmarks(fake, 0, 10, 4, 4, 11, 0, out.ctypes.data_as(P64), None) == 1
+    assert L.mds_maxmin_landmarks(fake, 0, 10, 4, 4, 3, 10, out.ctypes.data_as(P64), None) == 1
+    assert L.mds_maxmin_landmarks(fake, 0, 10, 4, 4, 3, 0, None, None) == 1
+    # pivot MDS: r >= l, l > n, duplicate pivots, ldy < r
+    assert L.mds_pivot_mds(fake, 0, 100, 4, 4, 5, 5, 0, None, fake, 5, lam, None, None) == 1
+    assert L.mds_pivot_mds(fake, 0, 100, 4, 4, 101, 2, 0, None, fake, 2, lam, None, None) == 1
+    dup = (ctypes.c_int64 * 3)(1, 4, 4)
+    assert L.mds_pivot_mds(fake, 0, 100, 4, 4, 3, 2, 0, dup, fake, 2, lam, None, None) == 1
+    assert L.mds_pivot_mds(fake, 0, 100, 4, 4, 10, 3, 0, None, fake, 2, lam, None, None) == 1
+    # dissimilarity input and affine form: NULL model / matrix
+    model = ctypes.c_void_p()
+    assert L.mds_fit_from_sqdist(None, 10, 10, 2, None, ctypes.byref(model)) == 1
+    assert L.mds_fit_from_sqdist(fake, 10, 9, 2, None, ctypes.byref(model)) == 1
+    assert L.mds_embed_from_sqdist(None, fake, 0, 10, 10, 1, fake, 2, None) == 1
+    assert L.mds_embed_affine(None, fake, 0, 10, 4, 1, fake, 2, None) == 1
