@@ -723,16 +723,15 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
 // ---- the same at large p when every landmark lo part is zero ----
 // (integer-valued landmarks, the usual case for image data).  The landmark
 // operands are then hi parts only, 32 KB per 512 x 32 chunk, which leaves
-// room for three chunk buffers (X FP32 16 KB + landmarks 32 KB each), so the
+// room for three chunk buffers (X 16 KB + landmarks 32 KB each), so the
 // copies run two chunks ahead of the MFMAs: data rows and landmarks both go
-// from memory straight into LDS, and each wave splits its own data
-// fragments into hi/lo after reading them (the four landmark quarters of a
-// row half split the same values, identically).  Barriers are raw s_barrier
-// with an explicit wait that leaves the newest chunk's copies in flight; a
-// compiler memory barrier keeps LDS accesses on their side of it.  The row
-// norms are summed by the consuming lanes themselves (8 columns each, then
-// a butterfly over the four lane groups).
-constexpr int WH_X = BM * CHUNK_BYTES;  // 128 rows x 32 FP32
+// from memory straight into LDS.  Each thread then splits its own two
+// 16-byte data segments in place (4 FP32 values -> 4 hi + 4 lo 16-bit
+// values in the same 16 bytes), so a lane reading the two segments of its
+// MFMA fragment gets hi and lo without further work.  Barriers are raw
+// s_barrier with an explicit wait that leaves the newest chunk's copies in
+// flight; a compiler memory barrier keeps LDS accesses on their side of it.
+constexpr int WH_X = BM * CHUNK_BYTES;  // 128 rows x 32 values
 constexpr int WH_ROW = 64;              // landmark hi part of one chunk
 constexpr int WH_BUF = WH_X + WBN * WH_ROW;
 constexpr int WH_NBUF = 3;
@@ -769,7 +768,6 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
   const int total = nch * nst;
   const bool xvec = ((((uintptr_t)X) & 15) == 0) && ((ldx * (int64_t)sizeof(float)) % 16 == 0);
   const bool xfast = xvec && (p % E == 0);
-  const int copies = xfast ? kWhCopiesFast : kWhCopiesSlow;
 
   f4 acc[8][4];  // [landmark block][row block]
   f4 yacc[4];
@@ -779,13 +777,13 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
 #pragma unroll
   for (int b = 0; b < 4; ++b) yacc[b] = f4{0, 0, 0, 0};
-  float nacc[4] = {0.f, 0.f, 0.f, 0.f};
+  float nacc[2] = {0.f, 0.f};
   float xn[4] = {0.f, 0.f, 0.f, 0.f};
 
   // data copies (fast path): wave copy u fills rows 64 u + 8 w .. + 8, lane
   // L the physical segment L % 8 of row L / 8 (logical (L % 8) ^ (row % 8));
   // rows past nrows repeat the last row and columns past p re-read the
-  // row's first columns (both finite, masked or discarded later)
+  // row's first columns (both finite; zeroed by the split)
   const int xsub = lane >> 3;
   const int xseg = (lane & 7) ^ xsub;
   const float* xsrc[2];
@@ -800,7 +798,7 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
   const int64_t mrow_bytes = (int64_t)nch * CHUNK_BYTES;
   const char* mlane = reinterpret_cast<const char*>(mv.mpack) +
                       (int64_t)(16 * wave + (lane >> 2)) * mrow_bytes + (((lane & 3) ^ ((lane >> 2) & 3)) << 4);
-  // slow path: register loads of 16-byte segments, zero outside the data
+  // the split: thread owns logical segment lseg of rows lrow + 64 u
   const int lrow = tid >> 3;
   const int lseg = tid & 7;
 
@@ -837,48 +835,62 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
                                        16, 0, 0);
   };
 
+  // in-place split of the thread's two segments of chunk (s, ch) in buffer b
+  auto split_chunk = [&](int b, int ch, bool norms) {
+    char* xb = lds + b * WH_BUF;
+    const int k0 = ch * 32 + lseg * E;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int row = lrow + 64 * u;
+      char* sp = xb + row * CHUNK_BYTES + swz(row, lseg);
+      f4 x = *reinterpret_cast<const f4*>(sp);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = (k0 + e < p) ? x[e] : 0.f;
+      if (norms) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) nacc[u] = fma(x[e], x[e], nacc[u]);
+      }
+      uint16_t hi[4], lo[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if constexpr (MODE == MODE_BF16) {
+          const __bf16 h = (__bf16)x[e];
+          const __bf16 lw = (__bf16)(x[e] - (float)h);
+          hi[e] = __builtin_bit_cast(uint16_t, h);
+          lo[e] = __builtin_bit_cast(uint16_t, lw);
+        } else {
+          const float xs = x[e] * mv.prescale;
+          const _Float16 h = (_Float16)xs;
+          const _Float16 lw = (_Float16)(xs - (float)h);
+          hi[e] = __builtin_bit_cast(uint16_t, h);
+          lo[e] = __builtin_bit_cast(uint16_t, lw);
+        }
+      }
+      const u4 packed = {(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16),
+                         (uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
+      *reinterpret_cast<u4*>(sp) = packed;
+    }
+  };
+
   // The products with the data lo parts are skipped when every lo part the
   // wave holds is zero: they would add exact zeros.
-  auto compute_chunk = [&](int b, int ch, bool norms) {
+  auto compute_chunk = [&](int b) {
     const char* xb = lds + b * WH_BUF;
     const char* mb = xb + WH_X;
-    const int kbase = ch * 32 + 8 * lg;
-    const bool ktail = ch * 32 + 32 > p;
     V bh[4], bl[4];
-    bool lo_nz = false;
+    uint32_t lo_or = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = 64 * wm + 16 * j + lr;
-      const f4 x0 = *reinterpret_cast<const f4*>(xb + row * CHUNK_BYTES + swz(row, 2 * lg));
-      const f4 x1 = *reinterpret_cast<const f4*>(xb + row * CHUNK_BYTES + swz(row, 2 * lg + 1));
-      float xv[8] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
-      if (ktail) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) xv[e] = (kbase + e < p) ? xv[e] : 0.f;
-      }
-      if (norms) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) nacc[j] = fma(xv[e], xv[e], nacc[j]);
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        if constexpr (MODE == MODE_BF16) {
-          const __bf16 h = (__bf16)xv[e];
-          const __bf16 lw = (__bf16)(xv[e] - (float)h);
-          bh[j][e] = h;
-          bl[j][e] = lw;
-          lo_nz |= ((float)lw != 0.0f);
-        } else {
-          const float x = xv[e] * mv.prescale;
-          const _Float16 h = (_Float16)x;
-          const _Float16 lw = (_Float16)(x - (float)h);
-          bh[j][e] = h;
-          bl[j][e] = lw;
-          lo_nz |= ((float)lw != 0.0f);
-        }
-      }
+      const u4 sa = *reinterpret_cast<const u4*>(xb + row * CHUNK_BYTES + swz(row, 2 * lg));
+      const u4 sb = *reinterpret_cast<const u4*>(xb + row * CHUNK_BYTES + swz(row, 2 * lg + 1));
+      const u4 h = {sa[0], sa[1], sb[0], sb[1]};
+      const u4 l = {sa[2], sa[3], sb[2], sb[3]};
+      bh[j] = __builtin_bit_cast(V, h);
+      bl[j] = __builtin_bit_cast(V, l);
+      lo_or |= (l[0] | l[1]) | (l[2] | l[3]);
     }
-    const bool do_xlo = __builtin_amdgcn_ballot_w64(lo_nz) != 0;
+    const bool do_xlo = __builtin_amdgcn_ballot_w64(lo_or != 0u) != 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int lm = 128 * wn + 16 * i + lr;
@@ -918,10 +930,14 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
   };
 
   // ---- pipeline: chunk it in buffer it % 3, copies two chunks ahead ----
+  // per chunk: copies of chunk it + 2 issued; split of chunk it (its copies
+  // landed before the previous barrier); barrier; MFMAs; wait for the copies
+  // of chunk it + 1; barrier
+  const int copies = xfast ? kWhCopiesFast : kWhCopiesSlow;
   issue(0, 0);
   if (total > 1) {
     issue(1, 1);
-    if (xfast) __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesFast));
+    if (copies == kWhCopiesFast) __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesFast));
     else __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesSlow));
   } else {
     __builtin_amdgcn_s_waitcnt(kWaitLgkVm(0));
@@ -933,17 +949,10 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
     const bool live = (int64_t)s * WBN + 128 * wn < l_pad;
     const bool ahead = it + 2 < total;
     if (ahead) issue(it + 2, b == 0 ? 2 : b - 1);
-    if (live) compute_chunk(b, ch, s == 0);
-    const bool tile_end = (ch == nch - 1);
-    if (tile_end && s == 0) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float t = nacc[j];
-        t += __shfl_xor(t, 16, 64);
-        t += __shfl_xor(t, 32, 64);
-        xn[j] = t;
-      }
-    }
+    split_chunk(b, ch, s == 0);
+    __builtin_amdgcn_s_waitcnt(kWaitLgkVm(15));  // the split's LDS stores
+    raw_barrier();
+    if (live) compute_chunk(b);
     // chunk it + 1 must have landed; the copies of chunk it + 2 may fly on
     if (ahead) {
       if (copies == kWhCopiesFast) __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesFast));
@@ -952,6 +961,26 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
       __builtin_amdgcn_s_waitcnt(kWaitLgkVm(0));
     }
     raw_barrier();
+    const bool tile_end = (ch == nch - 1);
+    if (tile_end && s == 0) {
+      // row norms (8 lanes per row, fixed butterfly) through buffer b, which
+      // nothing touches again before the copies issued next iteration
+      float* xnorm = reinterpret_cast<float*>(lds + b * WH_BUF);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        float t = nacc[u];
+        t += __shfl_xor(t, 4, 64);
+        t += __shfl_xor(t, 2, 64);
+        t += __shfl_xor(t, 1, 64);
+        if (lseg == 0) xnorm[lrow + 64 * u] = t;
+      }
+      __builtin_amdgcn_s_waitcnt(kWaitLgkVm(15));
+      raw_barrier();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xn[j] = xnorm[64 * wm + 16 * j + lr];
+      __builtin_amdgcn_s_waitcnt(kWaitLgkVm(15));
+      raw_barrier();
+    }
     if (tile_end && live) epilogue(s);
     b = (b == 2) ? 0 : b + 1;
   }
