@@ -454,8 +454,12 @@ static_assert(WBN == kSplitPackRows, "split packs are padded for this variant");
 // s_waitcnt immediate for vmcnt(0) with the other counters left alone
 constexpr int kWaitVm0 = 0x0F70;
 
-// byte offset of 16-byte segment seg (0..7) in a 128-byte row of LDS
-__device__ inline int swz(int row, int seg) { return (seg ^ (row & 7)) << 4; }
+// byte offset of 16-byte segment seg (0..7) in a 128-byte row of LDS: the
+// XOR with bits 1..3 of the row puts the 16 rows read by 16 lanes (row
+// pairs share a 256-byte line) on distinct 16-byte slots
+__device__ inline int swz(int row, int seg) { return (seg ^ ((row >> 1) & 7)) << 4; }
+// the same for 64-byte rows (four segments): bits 2..3 of the row
+__device__ inline int swz64(int row, int seg) { return (seg ^ ((row >> 2) & 3)) << 4; }
 
 template <int MODE>
 __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restrict__ X, int64_t ldx,
@@ -497,10 +501,11 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   // Landmark operands go from memory straight into LDS (16 bytes per lane,
   // no registers): wave load u of wave w fills the 1 KB of landmark rows
   // 64 u + 8 w .. + 8, lane L the physical segment L % 8 of row L / 8, so
-  // it fetches the logical segment (L % 8) ^ (row % 8).
+  // it fetches the logical segment (L % 8) ^ ((row / 2) % 8).
   const int64_t mrow_bytes = (int64_t)nch * CHUNK_BYTES;
   const char* mlane = reinterpret_cast<const char*>(mv.mpack) +
-                      (int64_t)(8 * wave + (lane >> 3)) * mrow_bytes + (((lane & 7) ^ (lane >> 3)) << 4);
+                      (int64_t)(8 * wave + (lane >> 3)) * mrow_bytes +
+                      (((lane & 7) ^ ((4 * (wave & 1) + (lane >> 4)) & 7)) << 4);
   auto dma_chunk = [&](int s, int ch, int buf) {
     char* mb = lds + buf * WBUF_BYTES + WX_BYTES + 8 * wave * CHUNK_BYTES;
     const char* src = mlane + (int64_t)s * WBN * mrow_bytes + (int64_t)ch * CHUNK_BYTES;
@@ -781,11 +786,11 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
   float xn[4] = {0.f, 0.f, 0.f, 0.f};
 
   // data copies (fast path): wave copy u fills rows 64 u + 8 w .. + 8, lane
-  // L the physical segment L % 8 of row L / 8 (logical (L % 8) ^ (row % 8));
+  // L the physical segment L % 8 of row L / 8 (logical (L % 8) ^ ((row / 2) % 8));
   // rows past nrows repeat the last row and columns past p re-read the
   // row's first columns (both finite; zeroed by the split)
   const int xsub = lane >> 3;
-  const int xseg = (lane & 7) ^ xsub;
+  const int xseg = (lane & 7) ^ ((4 * (wave & 1) + (lane >> 4)) & 7);
   const float* xsrc[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -794,10 +799,10 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
   }
   // landmark copies: wave copy u fills landmark rows 128 u + 16 w .. + 16
   // (64 bytes each), lane L the physical segment L % 4 of row L / 4
-  // (logical (L % 4) ^ (row % 4)); the hi half of each packed chunk
+  // (logical (L % 4) ^ ((row / 4) % 4)); the hi half of each packed chunk
   const int64_t mrow_bytes = (int64_t)nch * CHUNK_BYTES;
   const char* mlane = reinterpret_cast<const char*>(mv.mpack) +
-                      (int64_t)(16 * wave + (lane >> 2)) * mrow_bytes + (((lane & 3) ^ ((lane >> 2) & 3)) << 4);
+                      (int64_t)(16 * wave + (lane >> 2)) * mrow_bytes + (((lane & 3) ^ ((lane >> 4) & 3)) << 4);
   // the split: thread owns logical segment lseg of rows lrow + 64 u
   const int lrow = tid >> 3;
   const int lseg = tid & 7;
@@ -894,7 +899,7 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int lm = 128 * wn + 16 * i + lr;
-      const V ah = *reinterpret_cast<const V*>(mb + lm * WH_ROW + ((lg ^ (lm & 3)) << 4));
+      const V ah = *reinterpret_cast<const V*>(mb + lm * WH_ROW + swz64(lm, lg));
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if constexpr (MODE == MODE_BF16) {
