@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "mds_internal.h"
@@ -298,7 +299,13 @@ __global__ __launch_bounds__(1024) void k_set_column(double* __restrict__ V, int
 // (multisection over the 256 threads) and their eigenvectors by inverse
 // iteration with partial pivoting, orthogonalising within clusters.
 // Output: theta[t], bound[t] = |beta[k-1] * s_{k-1,t}| (Lanczos residual
-// norm of Ritz pair t), S[t*ldS + i], and kout[0] = k.
+// norm of Ritz pair t), S[t*ldS + i], and kout[0] = k.  With report given,
+// it also receives the 16 control words (word 6 = k) and, as double 8, qn[0],
+// so that one copy brings the host everything a convergence check needs.
+// A second block (grid of 2) solves the leading (k - d_probe) x (k - d_probe)
+// matrix, i.e. the Ritz pairs d_probe steps earlier, into theta2/bound2
+// (S2, gwork2 its own work space): with both the host can estimate how fast
+// the residual bounds fall.
 
 __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alpha,
                                                  const double* __restrict__ beta,
@@ -307,11 +314,25 @@ __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alph
                                                  double* __restrict__ bound_out,
                                                  double* __restrict__ S, int ldS,
                                                  double* __restrict__ gwork, int* __restrict__ kout,
-                                                 int work_in_lds) {
+                                                 int work_in_lds, double* __restrict__ report,
+                                                 const double* __restrict__ qn, int d_probe,
+                                                 double* __restrict__ theta2,
+                                                 double* __restrict__ bound2,
+                                                 double* __restrict__ S2,
+                                                 double* __restrict__ gwork2) {
   extern __shared__ double sm[];
   __shared__ double theta[MDS_MAX_R];
   const int t = threadIdx.x;
-  const int k = ctrl[0] ? ctrl[1] + 1 : k_host;
+  const bool probe = blockIdx.x == 1;
+  const int kfull = ctrl[0] ? ctrl[1] + 1 : k_host;
+  const int k = probe ? kfull - d_probe : kfull;
+  if (k < 1) return;  // (probe only: the host ignores its output then)
+  if (probe) {
+    theta_out = theta2;
+    bound_out = bound2;
+    S = S2;
+    gwork = gwork2;
+  }
   const int nr = min(r, k);
   double* al = sm;
   double* be = sm + k;
@@ -328,7 +349,12 @@ __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alph
     theta_out[t] = theta[t];
     bound_out[t] = coupling * fabs(S[(int64_t)t * ldS + (k - 1)]);
   }
+  if (probe) return;
   if (t == 0) kout[0] = k;
+  if (report) {
+    if (t < 16) reinterpret_cast<int*>(report)[t] = (t == 6) ? k : ctrl[t];
+    if (t == 16) report[8] = qn[0];
+  }
 }
 
 // Ritz vectors V_r[i][t] = sum_c Vk[c][i] S[t][c]   (output row-major l x r)
@@ -586,7 +612,9 @@ constexpr size_t kTriLdsMax = 150 * 1024;
 // when they fit.
 hipError_t launch_tridiag(const double* alpha, const double* beta, const int* ctrl, int k_host,
                           int r, double* theta, double* bound, double* S, int ldS, double* gwork,
-                          int* kout, hipStream_t st) {
+                          int* kout, hipStream_t st, double* report = nullptr,
+                          const double* qn = nullptr, int d_probe = 0, double* theta2 = nullptr,
+                          double* bound2 = nullptr, double* S2 = nullptr, double* gwork2 = nullptr) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tridiag),
@@ -598,8 +626,10 @@ hipError_t launch_tridiag(const double* alpha, const double* beta, const int* ct
   const size_t base = sizeof(double) * 3 * (size_t)k_host;
   const size_t work = sizeof(double) * 4 * (size_t)k_host * nr;
   const int in_lds = (base + work <= kTriLdsMax) ? 1 : 0;
-  k_tridiag<<<1, 256, base + (in_lds ? work : 0), st>>>(alpha, beta, ctrl, k_host, r, theta, bound, S,
-                                                       ldS, gwork, kout, in_lds);
+  const unsigned grid = (d_probe > 0) ? 2u : 1u;
+  k_tridiag<<<grid, 256, base + (in_lds ? work : 0), st>>>(alpha, beta, ctrl, k_host, r, theta, bound, S,
+                                                          ldS, gwork, kout, in_lds, report, qn, d_probe,
+                                                          theta2, bound2, S2, gwork2);
   return hipGetLastError();
 }
 
@@ -671,15 +701,15 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   bV.st = st;
   MDS_HIP(hipMallocAsync(&bsmall.p, sizeof(double) * ((size_t)l * 7 + 64), st));
   bsmall.st = st;
-  MDS_HIP(hipMallocAsync(&bS.p, sizeof(double) * (size_t)(kcap + 1) * (r + 1), st));
+  MDS_HIP(hipMallocAsync(&bS.p, sizeof(double) * (size_t)(kcap + 1) * (2 * r + 1), st));
   bS.st = st;
-  MDS_HIP(hipMallocAsync(&bwork.p, sizeof(double) * (size_t)(kcap + 1) * 4 * (r + 1), st));
+  MDS_HIP(hipMallocAsync(&bwork.p, sizeof(double) * (size_t)(kcap + 1) * 4 * (2 * r + 1), st));
   bwork.st = st;
   MDS_HIP(hipMallocAsync(&bVr.p, sizeof(double) * l * r, st));
   bVr.st = st;
   MDS_HIP(hipMallocAsync(&bX1.p, sizeof(double) * l * r, st));
   bX1.st = st;
-  MDS_HIP(hipMallocAsync(&bab.p, sizeof(double) * ((size_t)2 * (kcap + 1) + 4 * MDS_MAX_R + 8), st));
+  MDS_HIP(hipMallocAsync(&bab.p, sizeof(double) * ((size_t)2 * (kcap + 1) + 6 * MDS_MAX_R + 32), st));
   bab.st = st;
   double* DQ = (double*)bDQ.p;
   double* Vk = (double*)bV.p;
@@ -692,14 +722,20 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   double* rowmax = h2 + l;
   double* scal = rowmax + l;  // [0] dbar, [1] |Q|_F, [2..3] FP16 scales (as floats)
   float* scales = reinterpret_cast<float*>(scal + 2);
-  // ctrl: [0] stop, [1] stop step, [2] ok, [3] bad input, [4..5] lo flags,
-  // [6] k of the last tridiagonal solve, [7] always 0 (no-stop view),
-  // [8] k of the newest-run solve
+  // ctrl: [0] stop, [1] stop step, [2] ok, [3] bad input, [4] asymmetric
+  // input, [6] k of the last tridiagonal solve, [7] always 0 (no-stop view),
+  // [8] k of the newest-run solve, [10..11] lo flags of the split packs
   int* ctrl = reinterpret_cast<int*>(scal + 8);
   double* alpha = (double*)bab.p;
   double* beta = alpha + (kcap + 1);
-  double* theta = beta + (kcap + 1);
+  // check report: 16 control words (8 doubles), qn, then theta and bound,
+  // read back with one copy
+  double* report = beta + (kcap + 1);
+  double* theta = report + 16;
   double* bound = theta + 2 * MDS_MAX_R;
+  double* theta2 = bound + 2 * MDS_MAX_R;  // the probe's pairs (d_probe steps earlier)
+  double* bound2 = theta2 + MDS_MAX_R;
+  const size_t report_doubles = 16 + 6 * MDS_MAX_R;
   MDS_HIP(hipMemsetAsync(ctrl, 0, sizeof(int) * 16, st));
   MDS_HIP(hipMemsetAsync(beta, 0, sizeof(double) * (kcap + 1), st));
 
@@ -727,18 +763,11 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   k_centre<<<(unsigned)l, 256, 0, st>>>(DQ, l, d1, scal, q, rowsq);
   k_sqrt_sum<<<1, 256, 0, st>>>(rowsq, l, scal + 1);
   LAUNCH_CHECK("centring");
+  // The input flags and |Q1|_F are read with the first convergence check
+  // (no host round trip here); on bad input the first batch of Lanczos
+  // steps runs on meaningless values and is discarded.
   int hctrl[16];
-  double hscal[2];
-  MDS_HIP(hipMemcpyAsync(hctrl, ctrl, sizeof(hctrl), hipMemcpyDeviceToHost, st));
-  MDS_HIP(hipMemcpyAsync(hscal, scal, sizeof(hscal), hipMemcpyDeviceToHost, st));
-  MDS_HIP(hipStreamSynchronize(st));
-  if (hctrl[3])
-    return set_error(MDS_ERR_INVALID_ARG, vectors ? "non-finite value in a landmark row"
-                                                  : "non-finite squared dissimilarity");
-  if (!vectors && hctrl[4]) return set_error(MDS_ERR_INVALID_ARG, "dissimilarity matrix is not symmetric");
-  MDS_HIP(hipMemsetAsync(ctrl + 3, 0, sizeof(int) * 2, st));
-  const double qnorm = hscal[1];
-  if (!(qnorm > 0.0)) return set_error(MDS_ERR_DEGENERATE, "all landmarks coincide (Q1 = 0)");
+  std::vector<double> hrep(report_doubles);
 
   // ---- Lanczos with full reorthogonalisation ----
   const int upd_blocks = (int)((l + 63) / 64);
@@ -754,7 +783,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   int k_final = 0;
   // Steps until the next convergence check: grown from the observed decay
   // rate of the slowest residual bound (a check costs a host round trip).
-  int batch = std::max(8, r + 2);
+  int batch = std::max(8, 2 * r + 4);
   int prev_j = -1;
   double prev_worst = 0.0;
   for (;;) {
@@ -770,12 +799,32 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
                                    (j + 1 < kcap) ? 1 : 0);
     }
     LAUNCH_CHECK("lanczos steps");
+    // the probe solves the Krylov matrix d_probe steps back (same run only)
+    const int d_probe = (j - block_start >= r + 4) ? std::max(4, (j - block_start) / 4) : 0;
     MDS_HIP(launch_tridiag(alpha, beta, ctrl, j, r, theta, bound, (double*)bS.p, kcap + 1,
-                           (double*)bwork.p, ctrl + 6, st));
-    MDS_HIP(hipMemcpyAsync(hctrl, ctrl, sizeof(hctrl), hipMemcpyDeviceToHost, st));
-    MDS_HIP(hipMemcpyAsync(htheta.data(), theta, sizeof(double) * r, hipMemcpyDeviceToHost, st));
-    MDS_HIP(hipMemcpyAsync(hbound.data(), bound, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+                           (double*)bwork.p, ctrl + 6, st, report, scal + 1, d_probe, theta2, bound2,
+                           (double*)bS.p + (size_t)(kcap + 1) * (r + 1),
+                           (double*)bwork.p + (size_t)(kcap + 1) * 4 * (r + 1)));
+    MDS_HIP(hipMemcpyAsync(hrep.data(), report, sizeof(double) * report_doubles,
+                           hipMemcpyDeviceToHost, st));
     MDS_HIP(hipStreamSynchronize(st));
+    std::memcpy(hctrl, hrep.data(), sizeof(hctrl));
+    if (hctrl[3])
+      return set_error(MDS_ERR_INVALID_ARG, vectors ? "non-finite value in a landmark row"
+                                                    : "non-finite squared dissimilarity");
+    if (!vectors && hctrl[4]) return set_error(MDS_ERR_INVALID_ARG, "dissimilarity matrix is not symmetric");
+    if (!(hrep[8] > 0.0)) return set_error(MDS_ERR_DEGENERATE, "all landmarks coincide (Q1 = 0)");
+    for (int t = 0; t < r; ++t) {
+      htheta[t] = hrep[16 + t];
+      hbound[t] = hrep[16 + 2 * MDS_MAX_R + t];
+    }
+    // the probe's worst bound, when it saw the same run without a stop
+    double probe_worst = -1.0;
+    if (d_probe > 0 && hctrl[0] == 0 && j - d_probe >= r) {
+      probe_worst = 0.0;
+      for (int t = 0; t < r; ++t)
+        probe_worst = std::max(probe_worst, hrep[16 + 5 * MDS_MAX_R + t] / fabs(hrep[16 + 4 * MDS_MAX_R]));
+    }
     const int k = hctrl[6];
     const bool stopped = hctrl[0] != 0;
     bool conv = k >= r;
@@ -808,6 +857,10 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     {
       double worst = 0.0;
       for (int t = 0; t < std::min(r, k); ++t) worst = std::max(worst, hbound[t] / fabs(htheta[0]));
+      if (probe_worst > 0.0) {  // the rate from the probe d_probe steps back
+        prev_j = j - d_probe;
+        prev_worst = probe_worst;
+      }
       int next = 8;
       if (prev_j >= 0 && worst > 0.0 && prev_worst > worst && j > prev_j) {
         const double rate = (log(prev_worst) - log(worst)) / (double)(j - prev_j);  // per step
@@ -883,7 +936,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     const int64_t total = l_pad * (int64_t)nch32 * 32;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     k_pack32<<<grid, 256, 0, st>>>((const double*)m.m64, ldm, l_pad, p, nch32, (float*)m.m32,
-                                   (uint16_t*)m.mbf, (uint16_t*)m.mh, scales, ctrl + 4);
+                                   (uint16_t*)m.mbf, (uint16_t*)m.mh, scales, ctrl + 10);
     // landmark chunks for the affine map (each wave walks a few landmarks,
     // so the loop is not a chain of memory latencies): up to 64, partials
     // within 64 MB
@@ -914,8 +967,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   MDS_HIP(hipMemcpyAsync(hctrl, ctrl, sizeof(hctrl), hipMemcpyDeviceToHost, st));
   MDS_HIP(hipMemcpyAsync(hsc, scales, sizeof(hsc), hipMemcpyDeviceToHost, st));
   MDS_HIP(hipStreamSynchronize(st));
-  m.bf_lo_zero = hctrl[4] ? 0 : 1;
-  m.h_lo_zero = hctrl[5] ? 0 : 1;
+  m.bf_lo_zero = hctrl[10] ? 0 : 1;
+  m.h_lo_zero = hctrl[11] ? 0 : 1;
   m.h_prescale = hsc[0];
   m.h_postscale = hsc[1];
   return MDS_OK;
