@@ -618,7 +618,9 @@ def main():
         "embed_fp32_ms": t32 * 1e3, "embed_fp32_points_per_s": n / t32,
         "split_bf16": {"embed_ms": tbf * 1e3, "points_per_s": n / tbf, "speedup_vs_fp32": t32 / tbf,
                        "algorithmic_tflops": flops / tbf / 1e12,
-                       "frac_of_bf16_peak_algorithmic": flops / tbf / PEAK_BF16_MFMA},
+                       "frac_of_bf16_peak_algorithmic": flops / tbf / PEAK_BF16_MFMA,
+                       "kernel": ("k_embed_wide<BF16> (512 landmarks per pass over a row tile)"
+                                  if w["p"] >= 256 and w["r"] <= 16 else "k_embed<BF16>")},
         "split_fp16": {"embed_ms": t16 * 1e3, "points_per_s": n / t16, "speedup_vs_fp32": t32 / t16},
         "embed_fp64_ms": t64 * 1e3,
         "err_vs_gpu_fp64_all_rows": err_vs64,
