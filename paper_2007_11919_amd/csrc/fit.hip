@@ -865,7 +865,9 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
       if (prev_j >= 0 && worst > 0.0 && prev_worst > worst && j > prev_j) {
         const double rate = (log(prev_worst) - log(worst)) / (double)(j - prev_j);  // per step
         const double need = (log(worst) - log(conv_tol)) / rate;
-        next = (int)std::ceil(need * 1.05) + 1;
+        // the bounds fall faster as the Ritz values settle, so a long
+        // extrapolation overshoots: aim short of it and check again
+        next = (int)std::ceil(need > 10.0 ? 0.85 * need : need) + 1;
       } else if (prev_j >= 0) {
         next = std::max(8, j / 4);
       }
