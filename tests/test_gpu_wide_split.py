@@ -40,7 +40,9 @@ def gaussian(n, p, seed, extra=0):
     (301, 7, 1000, 16),   # odd p, strided rows, r at one full column block
     (256, 0, 512, 3),     # smallest p of the variant, one exact pass
     (784, 0, 2000, 10),   # the image shape with Gaussian values
-], ids=["p300", "p301-strided", "p256", "p784"])
+    (300, 0, 100, 4),     # 128 padded landmarks: three quarters idle in the only pass
+    (512, 0, 260, 10),    # 384 padded landmarks: one idle quarter
+], ids=["p300", "p301-strided", "p256", "p784", "l100", "l260"])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 def test_wide_split_matches_oracle(p, extra, l, r, prec):
     n = 2500
@@ -58,11 +60,13 @@ def test_wide_split_matches_oracle(p, extra, l, r, prec):
         assert np.array_equal(embed_np(model, Xd[:m], prec), full[:m]), m
 
 
-def test_wide_split_integer_data_and_batch_invariance():
+@pytest.mark.parametrize("l", [900, 200])
+def test_wide_split_integer_data_and_batch_invariance(l):
+    """Integer data (hi-only landmark form); l = 200 leaves idle quarters."""
     X = gen.image_mixture(3000, seed=21)
     Xd = torch.from_numpy(X).cuda()
-    model = mds().fit_landmarks(Xd, 900, 10, seed=4)
-    fit = oracle.fit_landmarks(X.astype(np.float64), 900, 10, seed=4)
+    model = mds().fit_landmarks(Xd, l, 10, seed=4)
+    fit = oracle.fit_landmarks(X.astype(np.float64), l, 10, seed=4)
     Yo = oracle.interpolate(fit, X.astype(np.float64))
     for prec in ("split_bf16", "split_fp16"):
         full = embed_np(model, Xd, prec)
