@@ -83,6 +83,17 @@ def time_embed(mds, torch, model, Xd, prec, iters):
     return e0.elapsed_time(e1) / 1e3 / iters, Y
 
 
+def embed_kernel(prec, p, l, r):
+    """Name of the embed kernel the library runs for a model of this shape
+    (same rule as the library's variant choice)."""
+    l_pad = -(-l // 128) * 128
+    span = -(-l_pad // 512) * 512
+    if r <= 16 and ((prec == "fp32" and l_pad >= 512 and 4 * (span - l_pad) < span)
+                    or (prec != "fp32" and p >= 256)):
+        return f"k_embed_wide<{prec.upper()}> (512 landmarks per pass over a row tile)"
+    return f"k_embed<{prec.upper()}> (128 landmarks per pass over a row tile)"
+
+
 def counters_for(kernel_tag):
     """Traffic measured by rocprofv3 --pmc for the current kernel source, or
     None if the source changed since the counters were taken."""
@@ -605,7 +616,7 @@ def main():
     tag = f"embed_fp32_{args.workload}"
     roof = {"bound": "mfma", "achieved": flops / t32 / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
             "unit": "TFLOP/s", "frac": flops / t32 / PEAK_FP32_MFMA,
-            "traffic": counters_for(tag), "kernel": "k_embed<FP32> (fused distance + projection)",
+            "traffic": counters_for(tag), "kernel": embed_kernel("fp32", w["p"], w["l"], w["r"]),
             "flops_per_point": fpp, "points_per_launch": n}
     out = {
         "metric": "embedded points/s, FP32 vs split-BF16 at stated err; serving p50/p99 latency",
@@ -619,8 +630,7 @@ def main():
         "split_bf16": {"embed_ms": tbf * 1e3, "points_per_s": n / tbf, "speedup_vs_fp32": t32 / tbf,
                        "algorithmic_tflops": flops / tbf / 1e12,
                        "frac_of_bf16_peak_algorithmic": flops / tbf / PEAK_BF16_MFMA,
-                       "kernel": ("k_embed_wide<BF16> (512 landmarks per pass over a row tile)"
-                                  if w["p"] >= 256 and w["r"] <= 16 else "k_embed<BF16>")},
+                       "kernel": embed_kernel("bf16", w["p"], w["l"], w["r"])},
         "split_fp16": {"embed_ms": t16 * 1e3, "points_per_s": n / t16, "speedup_vs_fp32": t32 / t16},
         "embed_fp64_ms": t64 * 1e3,
         "err_vs_gpu_fp64_all_rows": err_vs64,

@@ -21,7 +21,11 @@
 // the epilogue e = c - |x|^2 + 2 S runs in between on the accumulator.
 // The per-row reduction order is fixed (landmark tiles in order, then the
 // two landmark halves of a block in order), so a row's result does not
-// depend on the batch it arrives in.
+// depend on the batch it arrives in.  Models with one 16-column output
+// block run the 512-landmark variant further down when it pays (the choice
+// is a function of the model alone).  In FP32 the 16-value k-block holding
+// value p - 1 is stored transposed in the landmark pack and in LDS, so the
+// products past p can be skipped.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -210,16 +214,26 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
       }
   };
   // returns 1 if any lo part of this thread's data is nonzero (split modes)
-  auto store_chunk = [&](int buf) -> int {
+  auto store_chunk = [&](int buf, int ch) -> int {
     int lo_nz = 0;
     char* xb = Xs + buf * TILE_BYTES;
     char* mb = Ms + buf * TILE_BYTES;
+    // FP32 tail k-block (the one holding value p - 1 when p is not a
+    // multiple of 16) is stored transposed, as the FP32 landmark pack is
+    const bool tail = (MODE == MODE_F32) && (p - (ch * 32 + (lseg >> 2) * 16) < 16);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int row = lrow + 32 * u;
       if constexpr (MODE == MODE_F32) {
-        f4 v = {(float)xr[u].v[0], (float)xr[u].v[1], (float)xr[u].v[2], (float)xr[u].v[3]};
-        *reinterpret_cast<f4*>(xb + row * ROW_BYTES + lseg * 16) = v;
+        if (tail) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            *reinterpret_cast<float*>(xb + row * ROW_BYTES + (lseg >> 2) * 64 + c * 16 + (lseg & 3) * 4) =
+                (float)xr[u].v[c];
+        } else {
+          f4 v = {(float)xr[u].v[0], (float)xr[u].v[1], (float)xr[u].v[2], (float)xr[u].v[3]};
+          *reinterpret_cast<f4*>(xb + row * ROW_BYTES + lseg * 16) = v;
+        }
       } else if constexpr (MODE == MODE_F64) {
         d2 v = {(double)xr[u].v[0], (double)xr[u].v[1]};
         *reinterpret_cast<d2*>(xb + row * ROW_BYTES + lseg * 16) = v;
@@ -259,7 +273,8 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
     if constexpr (!SPLIT) {
 #pragma unroll
       for (int kb = 0; kb < Tt::KB; ++kb) {
-        if (ch * Tt::CH + kb * Tt::KBLK >= p) break;
+        const int rem = p - (ch * Tt::CH + kb * Tt::KBLK);
+        if (rem <= 0) break;
         using V = typename std::conditional<MODE == MODE_F64, d2, f4>::type;
         V b[4];
 #pragma unroll
@@ -270,8 +285,11 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
           const V a = *reinterpret_cast<const V*>(mb + (64 * wn + 16 * i + lr) * ROW_BYTES + kb * 64 + lg * 16);
 #pragma unroll
           for (int jj = 0; jj < 16 / (int)sizeof(T); ++jj)
+            // FP32 tail k-block (transposed): product jj holds values
+            // 4 jj .. 4 jj + 3, so those past p are skipped
+            if (MODE == MODE_F64 || 4 * jj < rem)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[jj], b[j][jj], acc[i][j]);
+              for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[jj], b[j][jj], acc[i][j]);
         }
       }
     } else {
@@ -356,7 +374,7 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
   load_chunk(0, 0);
   accumulate_norm();
   {
-    const int nz = store_chunk(0);
+    const int nz = store_chunk(0, 0);
     xlo_cur = __syncthreads_or(nz);
   }
   int lt = 0, ch = 0;
@@ -370,7 +388,7 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
     int nz = 0;
     if (has_next) {
       if (nlt == 0) accumulate_norm();
-      nz = store_chunk(buf ^ 1);
+      nz = store_chunk(buf ^ 1, nchn);
     }
     const bool tile_end = (ch == nch - 1);
     if (tile_end && lt == 0) {
@@ -429,27 +447,33 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
   __syncthreads();
 }
 
-// ---- split precisions at large p: 512 landmarks per pass over the row tile
-// With p in the hundreds a 128-row tile of X is too large to stay in L2
-// while the block walks the landmarks, so every landmark tile re-reads (and
-// re-splits) it from memory.  This variant keeps the 128-row tile but
-// walks the landmarks WBN = 512 at a time: eight waves as 2 row halves x 4
-// landmark quarters, each 64 rows x 128 landmarks of accumulators, so X is
-// read and split a quarter as often.  One chunk buffer (X hi/lo 16 KB +
-// landmarks 64 KB) is double-buffered, which fills the 160 KB of LDS;
-// 16-byte segments are XOR-swizzled by row instead of padded, and the
-// landmark operands are copied from memory straight into LDS (the split
-// packs are allocated to a multiple of WBN rows, zero past l_pad).  The row
-// norms pass once through the buffer just consumed.  The quarters are
-// added in order at the end.  The landmark order of the sums differs from
-// the 128-landmark variant, so each model and precision always runs the
-// same variant (plain and serving launches alike).
+// ---- 512 landmarks per pass over the row tile (FP32, and split
+// precisions at large p)
+// The 128-landmark kernel moves one 128 x 32 data chunk and one 128 x 32
+// landmark chunk through LDS per 128 x 128 x 32 block of products; its two
+// blocks per CU tend to run in phase, so the copies and barriers add to the
+// MFMA time instead of hiding under it.  With p in the hundreds a 128-row
+// tile of X is also too large to stay in L2 while the block walks the
+// landmarks, so every landmark tile re-reads (and, split, re-splits) it.
+// This variant keeps the 128-row tile but walks the landmarks WBN = 512 at a
+// time: eight waves as 2 row halves x 4 landmark quarters, each 64 rows x
+// 128 landmarks of accumulators, so a chunk copy feeds twice the products
+// and X is read a quarter as often.  One chunk buffer (X 16 KB + landmarks
+// 64 KB; FP32 values or hi/lo halves) is double-buffered, which fills the
+// 160 KB of LDS; 16-byte segments are XOR-swizzled by row instead of
+// padded, and the landmark operands are copied from memory straight into
+// LDS (the FP32 and split packs are allocated to a multiple of WBN rows,
+// zero past l_pad).  The row norms pass once through the buffer just
+// consumed.  The quarters are added in order at the end.  The landmark
+// order of the sums differs from the 128-landmark variant, so each model
+// and precision always runs the same variant (plain and serving launches
+// alike).
 constexpr int WBN = 512;
 constexpr int WTHREADS = 512;
 constexpr int WX_BYTES = BM * CHUNK_BYTES;
 constexpr int WBUF_BYTES = WX_BYTES + WBN * CHUNK_BYTES;
 constexpr int WLDS_BYTES = 2 * WBUF_BYTES;
-static_assert(WBN == kSplitPackRows, "split packs are padded for this variant");
+static_assert(WBN == kSplitPackRows, "landmark packs are padded for this variant");
 
 // s_waitcnt immediate for vmcnt(0) with the other counters left alone
 constexpr int kWaitVm0 = 0x0F70;
@@ -555,11 +579,26 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
 #pragma unroll
       for (int i = 0; i < E; ++i) nacc[u] = fma(xr[u].v[i], xr[u].v[i], nacc[u]);
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, int ch) {
     char* xb = lds + buf * WBUF_BYTES;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int row = lrow + 64 * u;
+      if constexpr (MODE == MODE_F32) {
+        if (p - (ch * 32 + (lseg >> 2) * 16) < 16) {
+          // tail k-block, transposed: value c of this segment goes to
+          // segment 4 (lseg / 4) + c, slot lseg % 4
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            *reinterpret_cast<float*>(xb + row * CHUNK_BYTES + swz(row, 4 * (lseg >> 2) + c) + 4 * (lseg & 3)) =
+                xr[u].v[c];
+        } else {
+          u4 v;
+          __builtin_memcpy(&v, &xr[u], 16);
+          *reinterpret_cast<u4*>(xb + row * CHUNK_BYTES + swz(row, lseg)) = v;
+        }
+        continue;
+      }
       uint16_t hi[4], lo[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -587,6 +626,34 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   };
   // The products with the data lo parts are skipped when every lo part the
   // wave holds is zero (integer-valued data): they would add exact zeros.
+  // FP32: lane group g holds values 4 g .. 4 g + 3 of a k-block (the
+  // tail k-block is stored transposed, so that product jj holds values
+  // 4 jj .. 4 jj + 3 there and the products past p are skipped)
+  auto compute_chunk_f32 = [&](int buf, int ch) {
+    const char* xb = lds + buf * WBUF_BYTES;
+    const char* mb = xb + WX_BYTES;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const int rem = p - (ch * 32 + kb * 16);
+      if (rem <= 0) break;
+      f4 b[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 64 * wm + 16 * j + lr;
+        b[j] = *reinterpret_cast<const f4*>(xb + row * CHUNK_BYTES + swz(row, 4 * kb + lg));
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int lm = 128 * wn + 16 * i + lr;
+        const f4 a = *reinterpret_cast<const f4*>(mb + lm * CHUNK_BYTES + swz(lm, 4 * kb + lg));
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          if (4 * jj < rem)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[jj], b[j][jj], acc[i][j]);
+      }
+    }
+  };
   auto compute_chunk = [&](int buf) {
     const char* xb = lds + buf * WBUF_BYTES;
     const char* mb = xb + WX_BYTES;
@@ -650,7 +717,7 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   dma_chunk(0, 0, 0);
   load_chunk(0);
   accumulate_norm();
-  store_chunk(0);
+  store_chunk(0, 0);
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
   int s = 0, ch = 0;
@@ -665,10 +732,15 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
       dma_chunk(nsn, nchn, buf ^ 1);
       load_chunk(nchn);
     }
-    if (live) compute_chunk(buf);
+    if (live) {
+      if constexpr (MODE == MODE_F32)
+        compute_chunk_f32(buf, ch);
+      else
+        compute_chunk(buf);
+    }
     if (has_next) {
       if (nsn == 0) accumulate_norm();
-      store_chunk(buf ^ 1);
+      store_chunk(buf ^ 1, nchn);
     }
     const bool tile_end = (ch == nch - 1);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
@@ -1152,8 +1224,11 @@ hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int
 template <int MODE>
 hipError_t launch_wide(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                        int64_t ldy, hipStream_t st) {
-  return mv.m_lo_zero ? launch_wide_v<MODE, true>(mv, X, n, ldx, Y, ldy, st)
-                      : launch_wide_v<MODE, false>(mv, X, n, ldx, Y, ldy, st);
+  if constexpr (MODE == MODE_F32)
+    return launch_wide_v<MODE, false>(mv, X, n, ldx, Y, ldy, st);
+  else
+    return mv.m_lo_zero ? launch_wide_v<MODE, true>(mv, X, n, ldx, Y, ldy, st)
+                        : launch_wide_v<MODE, false>(mv, X, n, ldx, Y, ldy, st);
 }
 
 template <int MODE, typename TX>
@@ -1222,14 +1297,15 @@ mds_status launch_embed(const Model& m, int mode, const void* X, int dt, int64_t
                           : launch_rb<MODE_F64, float>(mv, X, n, ldx, Y, ldy, st);
       break;
     case MODE_F32:
-      e = launch_rb<MODE_F32, float>(mv, X, n, ldx, Y, ldy, st);
+      e = embed_wide(mode, m.p, m.rb, m.l_pad) ? launch_wide<MODE_F32>(mv, X, n, ldx, Y, ldy, st)
+                                      : launch_rb<MODE_F32, float>(mv, X, n, ldx, Y, ldy, st);
       break;
     case MODE_BF16:
-      e = embed_wide(mode, m.p, m.rb) ? launch_wide<MODE_BF16>(mv, X, n, ldx, Y, ldy, st)
+      e = embed_wide(mode, m.p, m.rb, m.l_pad) ? launch_wide<MODE_BF16>(mv, X, n, ldx, Y, ldy, st)
                                       : launch_rb<MODE_BF16, float>(mv, X, n, ldx, Y, ldy, st);
       break;
     default:
-      e = embed_wide(mode, m.p, m.rb) ? launch_wide<MODE_F16>(mv, X, n, ldx, Y, ldy, st)
+      e = embed_wide(mode, m.p, m.rb, m.l_pad) ? launch_wide<MODE_F16>(mv, X, n, ldx, Y, ldy, st)
                                       : launch_rb<MODE_F16, float>(mv, X, n, ldx, Y, ldy, st);
       break;
   }
@@ -1244,9 +1320,7 @@ const void* worklist_fn_rb(int rbc) {
     case 0: return reinterpret_cast<const void*>(&k_embed_work<MODE, 1>);
     case 1: return reinterpret_cast<const void*>(&k_embed_work<MODE, 2>);
     case 2: return reinterpret_cast<const void*>(&k_embed_work<MODE, 4>);
-    case kWideClass:
-      if constexpr (MODE == MODE_F32) return nullptr;
-      else return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, false>);
+    case kWideClass: return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, false>);
     default:
       if constexpr (MODE == MODE_F32) return nullptr;
       else return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, true>);
@@ -1269,10 +1343,7 @@ void launch_work_rb(int rbc, int grid, hipStream_t st, const EmbedModelView* v, 
     case 0: k_embed_work<MODE, 1><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
     case 1: k_embed_work<MODE, 2><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
     case 2: k_embed_work<MODE, 4><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
-    case kWideClass:
-      if constexpr (MODE != MODE_F32)
-        k_embed_work_wide<MODE, false><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw);
-      break;
+    case kWideClass: k_embed_work_wide<MODE, false><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw); break;
     default:
       if constexpr (MODE != MODE_F32)
         k_embed_work_wide<MODE, true><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw);
@@ -1283,9 +1354,9 @@ void launch_work_rb(int rbc, int grid, hipStream_t st, const EmbedModelView* v, 
 
 int rb_class(int rb) { return rb <= 1 ? 0 : (rb == 2 ? 1 : 2); }
 
-int embed_class(int mode, int64_t p, int rb, int m_lo_zero) {
-  if (!embed_wide(mode, p, rb)) return rb_class(rb);
-  return m_lo_zero ? kWideHiClass : kWideClass;
+int embed_class(int mode, int64_t p, int rb, int64_t l_pad, int m_lo_zero) {
+  if (!embed_wide(mode, p, rb, l_pad)) return rb_class(rb);
+  return (m_lo_zero && mode != MODE_F32) ? kWideHiClass : kWideClass;
 }
 
 int embed_blocks_per_cu(int mode, int rbc) {

@@ -572,7 +572,14 @@ __global__ void k_pack32(const double* __restrict__ M, int64_t ldm, int64_t l_pa
     const int ch = (int)(rem >> 5), kk = (int)(rem & 31);
     const int64_t k = (int64_t)ch * 32 + kk;
     const float x = (k < p) ? (float)M[row * ldm + k] : 0.0f;
-    m32[e] = x;
+    // FP32 pack: the 16-value k-block holding value p - 1 (p not a multiple
+    // of 16) is transposed, value 4 a + b at position 4 b + a, so that each
+    // group of four MFMA inputs holds consecutive values and the embed can
+    // skip those past p
+    const int kb0 = ch * 32 + (kk & 16);
+    const int kin = kk & 15;
+    const int kdst = (p - kb0 < 16) ? ((kin & 3) * 4 + (kin >> 2)) : kin;
+    m32[e - kin + kdst] = x;
     const __bf16 bh = (__bf16)x;
     const __bf16 bl = (__bf16)(x - (float)bh);
     const int64_t base = (row * nch + ch) * 64;
@@ -658,9 +665,10 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   // ---- model buffers: one allocation ----
   Layout lay;
   const size_t o64 = lay.take(sizeof(double) * l_pad * ldm);
-  const size_t o32 = lay.take(sizeof(float) * l_pad * nch32 * 32);
-  // split packs: rows up to a multiple of kSplitPackRows (zero past l_pad)
+  // FP32 and split packs: rows up to a multiple of kSplitPackRows (zero past
+  // l_pad) for the variant of the embed that walks 512 landmarks at a time
   const int64_t l_split = round_up(l_pad, kSplitPackRows);
+  const size_t o32 = lay.take(sizeof(float) * l_split * nch32 * 32);
   const size_t obf = lay.take(sizeof(uint16_t) * l_split * nch32 * 64);
   const size_t oh = lay.take(sizeof(uint16_t) * l_split * nch32 * 64);
   const size_t ow32 = lay.take(sizeof(float) * l_pad * ldw);

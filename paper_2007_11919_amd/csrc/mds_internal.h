@@ -27,17 +27,24 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 // elements of the contraction per chunk in each mode
 inline int chunk_elems(int mode) { return mode == MODE_F64 ? 16 : 32; }
 
-// Split-precision models with one 16-column output block and p >= kWideMinP
-// run the variant of the embed kernel that walks the landmarks 512 at a time
-// (plain and serving launches alike, so a row's result does not depend on
-// the launch it arrives in).
+// Models with one 16-column output block run the variant of the embed kernel
+// that walks the landmarks 512 at a time when it pays: FP32 when at least
+// 512 landmark rows are padded and fewer than a quarter of the last
+// 512-landmark pass would be idle; split precisions when p >= kWideMinP.
+// The choice depends on the model only (plain and serving launches alike),
+// so a row's result does not depend on the launch it arrives in.
 constexpr int kWideMinP = 256;
-constexpr int kSplitPackRows = 512;  // split packs hold round_up(l_pad, this) rows
+constexpr int kSplitPackRows = 512;  // landmark packs hold round_up(l_pad, this) rows
 constexpr int kEmbedClasses = 5;
-constexpr int kWideClass = 3;    // wide variant, landmark lo parts present
-constexpr int kWideHiClass = 4;  // wide variant, landmark lo parts all zero
-inline bool embed_wide(int mode, int64_t p, int rb) {
-  return (mode == MODE_BF16 || mode == MODE_F16) && rb == 1 && p >= kWideMinP;
+constexpr int kWideClass = 3;    // wide variant (FP32, or split with landmark lo parts)
+constexpr int kWideHiClass = 4;  // wide split variant, landmark lo parts all zero
+inline bool embed_wide(int mode, int64_t p, int rb, int64_t l_pad) {
+  if (rb != 1) return false;
+  if (mode == MODE_F32) {
+    const int64_t span = round_up(l_pad, kSplitPackRows);
+    return l_pad >= kSplitPackRows && 4 * (span - l_pad) < span;
+  }
+  return (mode == MODE_BF16 || mode == MODE_F16) && p >= kWideMinP;
 }
 
 // Device-side view of one model for one precision, passed by value.
@@ -81,7 +88,7 @@ struct Model {
   // device buffers: one allocation (base), the rest point into it
   void* base = nullptr;
   void* m64 = nullptr;    // l_pad x nchunks64 x 16 doubles (FP64 operand and fit input)
-  void* m32 = nullptr;    // l_pad x nchunks32 x 32 floats
+  void* m32 = nullptr;    // round_up(l_pad, kSplitPackRows) x nchunks32 x 32 floats
   void* mbf = nullptr;    // l_pad x nchunks32 x (32 hi + 32 lo) bf16
   void* mh = nullptr;     // same for FP16 (scaled)
   void* w32 = nullptr;    // 16rb x l_pad float (column-major: output column, landmark)
@@ -155,13 +162,13 @@ mds_status launch_embed_sqdist(const Model& m, int prec64, const void* A2, int d
                                int64_t lda, void* Y, int64_t ldy, hipStream_t st);
 // persistent serving launch over a device table of tiles
 // rbc = embed_class(...): 0 for rb 1, 1 for rb 2, 2 for rb 3..4, and
-// kWideClass / kWideHiClass for the 512-landmark split-precision variants
+// kWideClass / kWideHiClass for the 512-landmark variants
 mds_status launch_embed_worklist(int mode, int rbc, const EmbedModelView* views_dev,
                                  const TileWork* work_dev, const int32_t* nwork_dev,
                                  int grid, hipStream_t st);
 int embed_max_rb();
 int rb_class(int rb);
-int embed_class(int mode, int64_t p, int rb, int m_lo_zero);
+int embed_class(int mode, int64_t p, int rb, int64_t l_pad, int m_lo_zero);
 int embed_blocks_per_cu(int mode, int rbc);
 mds_status prepare_embed_worklist(int mode, int rbc);
 

@@ -254,7 +254,7 @@ void worker_main(mds_server* s) {
 mds_status capture_graphs(mds_server* s) {
   for (int mi = 0; mi < kModes; ++mi)
     for (int rbc = 0; rbc < kRbc; ++rbc) {
-      if (mode_of_index(mi) == MODE_F32 && rbc >= kWideClass) continue;  // no such launch
+      if (mode_of_index(mi) == MODE_F32 && rbc == kWideHiClass) continue;  // no such launch
       mds_status st = prepare_embed_worklist(mode_of_index(mi), rbc);
       if (st != MDS_OK) return st;
     }
@@ -262,7 +262,7 @@ mds_status capture_graphs(mds_server* s) {
     Slot& sl = s->slots[k];
     for (int gi = 0; gi < kGraphs; ++gi) {
       const int mi = gi / kRbc, rbc = gi % kRbc;
-      if (mode_of_index(mi) == MODE_F32 && rbc >= kWideClass) continue;
+      if (mode_of_index(mi) == MODE_F32 && rbc == kWideHiClass) continue;
       MDS_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipMemcpyAsync(sl.dev, sl.host, slot_bytes(s->tiles_cap), hipMemcpyHostToDevice,
                                     s->stream);
@@ -404,7 +404,7 @@ mds_status mds_serve_submit(mds_server* s, int32_t model_id, const void* X, int6
   Request rq;
   rq.model = model_id;
   rq.mode = mode;
-  rq.rbc = embed_class(mode, m->p, m->rb, mode == MODE_BF16 ? m->bf_lo_zero : m->h_lo_zero);
+  rq.rbc = embed_class(mode, m->p, m->rb, m->l_pad, mode == MODE_BF16 ? m->bf_lo_zero : m->h_lo_zero);
   rq.x = X;
   rq.y = Y;
   rq.n = n_pts;
