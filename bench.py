@@ -88,8 +88,8 @@ def embed_kernel(prec, p, l, r):
     (same rule as the library's variant choice)."""
     l_pad = -(-l // 128) * 128
     span = -(-l_pad // 512) * 512
-    if r <= 16 and ((prec == "fp32" and l_pad >= 512 and 4 * (span - l_pad) < span)
-                    or (prec != "fp32" and p >= 256)):
+    fills = l_pad >= 512 and 4 * (span - l_pad) < span
+    if r <= 16 and (fills or (prec != "fp32" and p >= 256)):
         return f"k_embed_wide<{prec.upper()}> (512 landmarks per pass over a row tile)"
     return f"k_embed<{prec.upper()}> (128 landmarks per pass over a row tile)"
 

@@ -28,23 +28,23 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int chunk_elems(int mode) { return mode == MODE_F64 ? 16 : 32; }
 
 // Models with one 16-column output block run the variant of the embed kernel
-// that walks the landmarks 512 at a time when it pays: FP32 when at least
-// 512 landmark rows are padded and fewer than a quarter of the last
-// 512-landmark pass would be idle; split precisions when p >= kWideMinP.
-// The choice depends on the model only (plain and serving launches alike),
-// so a row's result does not depend on the launch it arrives in.
+// that walks the landmarks 512 at a time when it pays: when at least 512
+// landmark rows are padded and fewer than a quarter of the last 512-landmark
+// pass would be idle, and in the split precisions also whenever p >=
+// kWideMinP (a 128-row tile of X no longer stays in L2 across landmark
+// tiles).  The choice depends on the model only (plain and serving launches
+// alike), so a row's result does not depend on the launch it arrives in.
 constexpr int kWideMinP = 256;
 constexpr int kSplitPackRows = 512;  // landmark packs hold round_up(l_pad, this) rows
 constexpr int kEmbedClasses = 5;
 constexpr int kWideClass = 3;    // wide variant (FP32, or split with landmark lo parts)
 constexpr int kWideHiClass = 4;  // wide split variant, landmark lo parts all zero
 inline bool embed_wide(int mode, int64_t p, int rb, int64_t l_pad) {
-  if (rb != 1) return false;
-  if (mode == MODE_F32) {
-    const int64_t span = round_up(l_pad, kSplitPackRows);
-    return l_pad >= kSplitPackRows && 4 * (span - l_pad) < span;
-  }
-  return (mode == MODE_BF16 || mode == MODE_F16) && p >= kWideMinP;
+  if (rb != 1 || mode == MODE_F64) return false;
+  const int64_t span = round_up(l_pad, kSplitPackRows);
+  const bool fills = l_pad >= kSplitPackRows && 4 * (span - l_pad) < span;
+  if (mode == MODE_F32) return fills;
+  return fills || p >= kWideMinP;
 }
 
 // Device-side view of one model for one precision, passed by value.

@@ -1,5 +1,6 @@
-"""Split-precision embed at large p (the variant that walks the landmarks
-512 at a time) against the FP64 oracle, through the C ABI (needs a GPU).
+"""Split-precision embed in the variant that walks the landmarks 512 at a
+time (at large p, and at any p with enough landmarks to fill the passes)
+against the FP64 oracle, through the C ABI (needs a GPU).
 
 Covers: general FP32 data (nonzero lo parts), integer data (lo parts
 skipped), p not a multiple of 4 and strided rows (scalar loads), a landmark
@@ -58,6 +59,35 @@ def test_wide_split_matches_oracle(p, extra, l, r, prec):
     # ragged row counts (partial tiles): the same bits as inside the full run
     for m in (1, 127, 128, 129):
         assert np.array_equal(embed_np(model, Xd[:m], prec), full[:m]), m
+
+
+@pytest.mark.parametrize("p,extra,l,r", [
+    (100, 0, 1000, 10),   # the 10^6 x 100 shape: two whole passes
+    # odd p, strided rows; 896 padded landmarks: one idle quarter.  r = 10,
+    # the data's strong directions: columns beyond them (std 1, nearly
+    # degenerate eigenvalues) amplify the split's rounding by about 1/lambda
+    (33, 3, 800, 10),
+    (10, 0, 512, 2),      # one chunk of 32 values, one exact pass
+], ids=["p100", "p33-strided", "p10"])
+@pytest.mark.parametrize("integer", [False, True], ids=["float", "integer"])
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_wide_split_small_p(p, extra, l, r, integer, prec):
+    """Small p with enough landmarks to fill 512-landmark passes; integer-valued
+    data has all lo parts zero (the three-buffer landmark-hi form)."""
+    n = 2500
+    Xw = gaussian(n, max(p, 10), seed=40 + p, extra=extra)[:, :p + extra]
+    if integer:
+        Xw = np.rint(Xw).astype(np.float32)
+    X = np.ascontiguousarray(Xw[:, :p])
+    Xd = torch.from_numpy(np.ascontiguousarray(Xw)).cuda()[:, :p]
+    model = mds().fit_landmarks(Xd, l, r, seed=5)
+    fit = oracle.fit_landmarks(X.astype(np.float64), l, r, seed=5)
+    Yo = oracle.interpolate(fit, X.astype(np.float64))
+    full = embed_np(model, Xd, prec)
+    e = errors.column_errors(full, Yo)
+    assert e["rms_rel"] <= TOL, e
+    for s, m in [(0, 1), (0, 129), (700, 300), (2499, 1)]:
+        assert np.array_equal(embed_np(model, Xd[s:s + m], prec), full[s:s + m]), (s, m)
 
 
 @pytest.mark.parametrize("l", [900, 200])
