@@ -521,6 +521,10 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   float nacc[2] = {0.f, 0.f};
   float xn[4] = {0.f, 0.f, 0.f, 0.f};
   Seg<float, E> xr[2];
+  // FP32: each wave sums the squares of the data operands it reads in the
+  // first pass (lane (lr, g) holds a quarter of row 16 j + lr), so the row
+  // norms need no exchange, whichever way a chunk reached LDS
+  float nrm[4] = {0.f, 0.f, 0.f, 0.f};
 
   // Landmark operands go from memory straight into LDS (16 bytes per lane,
   // no registers): wave load u of wave w fills the 1 KB of landmark rows
@@ -540,22 +544,46 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
                                        16, 0, 0);
   };
 
-  // data rows: pointer to the lane's 16-byte slot of row lrow + 64 u (the
-  // last row stands in for rows past nrows, whose values are zeroed)
-  const float* xrow[2];
+  // FP32 data chunks without a ragged k-block also go straight to LDS when
+  // the rows are 16-byte aligned: wave copy u fills rows 64 u + 8 w .. + 8
+  // with the same lane mapping as the landmark copies.  Rows past nrows
+  // repeat the last row (their results are not stored); a segment that
+  // starts past p re-reads the row's first segment (its k-block is never
+  // computed), so every address stays inside the row.
+  // (row addresses are formed at each copy: fewer live registers)
+  const int xdseg = ((lane & 7) ^ ((4 * (wave & 1) + (lane >> 4)) & 7)) * E;
+  // the chunk holds no computed k-block with values past p
+  auto x_direct = [&](int ch) {
+    if (MODE != MODE_F32 || !xfast) return false;
+    const int r0 = p - ch * 32, r1 = r0 - 16;
+    return !(r0 > 0 && r0 < 16) && !(r1 > 0 && r1 < 16);
+  };
+  auto dma_x = [&](int ch, int buf) {
+    char* xb = lds + buf * WBUF_BYTES + 8 * wave * CHUNK_BYTES;
+    const int k = ch * 32 + xdseg;
+    const int64_t koff = k < p ? k : 0;
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int row = lrow + 64 * u;
-    xrow[u] = X + (int64_t)(row < nrows ? row : nrows - 1) * ldx + lseg * E;
-  }
+    for (int u = 0; u < 2; ++u) {
+      const int row = 64 * u + 8 * wave + (lane >> 3);
+      const float* src = X + (int64_t)(row < nrows ? row : nrows - 1) * ldx + koff;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                       (__attribute__((address_space(3))) void*)(xb + 64 * u * CHUNK_BYTES),
+                                       16, 0, 0);
+    }
+  };
+
   auto load_chunk = [&](int ch) {
     const int64_t k0 = (int64_t)ch * 32 + lseg * E;
     if (xfast) {
       const bool kin = k0 < p;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const bool in = kin && (lrow + 64 * u < nrows);
-        const u4 raw = *reinterpret_cast<const u4*>(xrow[u] + (kin ? (int64_t)ch * 32 : 0));
+        // the lane's 16-byte slot of row lrow + 64 u (the last row stands in
+        // for rows past nrows, whose values are zeroed)
+        const int row = lrow + 64 * u;
+        const float* xrow = X + (int64_t)(row < nrows ? row : nrows - 1) * ldx + lseg * E;
+        const bool in = kin && (row < nrows);
+        const u4 raw = *reinterpret_cast<const u4*>(xrow + (kin ? (int64_t)ch * 32 : 0));
         const u4 z = {0u, 0u, 0u, 0u};
         const u4 v = in ? raw : z;
         __builtin_memcpy(&xr[u], &v, 16);
@@ -629,7 +657,7 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   // FP32: lane group g holds values 4 g .. 4 g + 3 of a k-block (the
   // tail k-block is stored transposed, so that product jj holds values
   // 4 jj .. 4 jj + 3 there and the products past p are skipped)
-  auto compute_chunk_f32 = [&](int buf, int ch) {
+  auto compute_chunk_f32 = [&](int buf, int ch, bool norms) {
     const char* xb = lds + buf * WBUF_BYTES;
     const char* mb = xb + WX_BYTES;
 #pragma unroll
@@ -651,6 +679,13 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
           if (4 * jj < rem)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[jj], b[j][jj], acc[i][j]);
+      }
+      // after the products, so that no branch separates the operand loads
+      if (norms) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) nrm[j] = fma(b[j][c], b[j][c], nrm[j]);
       }
     }
   };
@@ -689,12 +724,12 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
     }
   };
   // e = c - |x|^2 + 2 s and Y^T += W^T E^T for the wave's quarter of super tile s
-  const float* cl = reinterpret_cast<const float*>(mv.c) + 128 * wn + 4 * lg;
-  const float* wl = reinterpret_cast<const float*>(mv.w) + (int64_t)lr * mv.ldwt + 128 * wn + 4 * lg;
   auto epilogue = [&](int s) {
     const float two = 2.0f * mv.postscale;
-    const float* cb = cl + (int64_t)s * WBN;
-    const float* wb = wl + (int64_t)s * WBN;
+    // (formed here rather than kept live across the chunk loop)
+    const float* cb = reinterpret_cast<const float*>(mv.c) + (int64_t)s * WBN + 128 * wn + 4 * lg;
+    const float* wb =
+        reinterpret_cast<const float*>(mv.w) + (int64_t)lr * mv.ldwt + (int64_t)s * WBN + 128 * wn + 4 * lg;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const f4 c4 = *reinterpret_cast<const f4*>(cb + 16 * i);
@@ -715,9 +750,13 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   // The landmark copies of a chunk are waited for (vmcnt) before the
   // barrier that publishes the chunk.
   dma_chunk(0, 0, 0);
-  load_chunk(0);
-  accumulate_norm();
-  store_chunk(0, 0);
+  if (x_direct(0)) {
+    dma_x(0, 0);
+  } else {
+    load_chunk(0);
+    if constexpr (MODE != MODE_F32) accumulate_norm();
+    store_chunk(0, 0);
+  }
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
   int s = 0, ch = 0;
@@ -728,18 +767,23 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
     const int nsn = (ch + 1 == nch) ? s + 1 : s;
     // a quarter wholly past the padded landmark count does no work
     const bool live = (int64_t)s * WBN + 128 * wn < l_pad;
+    const bool next_direct = has_next && x_direct(nchn);
     if (has_next) {
       dma_chunk(nsn, nchn, buf ^ 1);
-      load_chunk(nchn);
+      if (next_direct)
+        dma_x(nchn, buf ^ 1);
+      else
+        load_chunk(nchn);
     }
     if (live) {
       if constexpr (MODE == MODE_F32)
-        compute_chunk_f32(buf, ch);
+        compute_chunk_f32(buf, ch, s == 0);
       else
         compute_chunk(buf);
     }
-    if (has_next) {
-      if (nsn == 0) accumulate_norm();
+    if (has_next && !next_direct) {
+      if constexpr (MODE != MODE_F32)
+        if (nsn == 0) accumulate_norm();
       store_chunk(buf ^ 1, nchn);
     }
     const bool tile_end = (ch == nch - 1);
@@ -747,21 +791,33 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
     __syncthreads();
     if (tile_end) {
       if (s == 0) {
-        // row norms (8 lanes per row, fixed butterfly) through buffer buf,
-        // which nobody reads or writes again before the next store into it
-        float* xnorm = reinterpret_cast<float*>(lds + buf * WBUF_BYTES);
+        if constexpr (MODE == MODE_F32) {
+          // fixed butterfly over the four lane groups: every lane of a row
+          // gets the same bits
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          float t = nacc[u];
-          t += __shfl_xor(t, 4, 64);
-          t += __shfl_xor(t, 2, 64);
-          t += __shfl_xor(t, 1, 64);
-          if (lseg == 0) xnorm[lrow + 64 * u] = t;
+          for (int j = 0; j < 4; ++j) {
+            float t = nrm[j];
+            t += __shfl_xor(t, 16, 64);
+            t += __shfl_xor(t, 32, 64);
+            xn[j] = t;
+          }
+        } else {
+          // row norms (8 lanes per row, fixed butterfly) through buffer buf,
+          // which nobody reads or writes again before the next store into it
+          float* xnorm = reinterpret_cast<float*>(lds + buf * WBUF_BYTES);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            float t = nacc[u];
+            t += __shfl_xor(t, 4, 64);
+            t += __shfl_xor(t, 2, 64);
+            t += __shfl_xor(t, 1, 64);
+            if (lseg == 0) xnorm[lrow + 64 * u] = t;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < 4; ++j) xn[j] = xnorm[64 * wm + 16 * j + lr];
+          __syncthreads();
         }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xn[j] = xnorm[64 * wm + 16 * j + lr];
-        __syncthreads();
       }
       if (live) epilogue(s);
     }

@@ -5,6 +5,7 @@ The variant runs for models with one output column block and at least 512
 padded landmarks, when under a quarter of the last 512-landmark pass would
 be idle.  Covers: p with a ragged tail k-block (products past p skipped), p
 below one k-block, p not a multiple of 4 with strided rows (scalar loads),
+aligned strided rows (data chunks copied straight to LDS),
 idle landmark quarters in the last pass, ragged row counts, batch
 invariance, and serving requests of every precision against plain calls."""
 
@@ -45,7 +46,8 @@ def gaussian(n, p, seed, extra=0):
     (16, 0, 1300, 10),    # one whole k-block; three passes, the last with an idle quarter
     (47, 0, 1024, 5),     # p % 4 = 3: tail k-block of 15 values, scalar loads
     (784, 0, 2000, 10),   # the image shape with Gaussian values
-], ids=["p100", "p101-strided", "p3", "p16-l1300", "p47", "p784"])
+    (64, 4, 1024, 10),    # 16-byte aligned strided rows: data chunks copied straight to LDS
+], ids=["p100", "p101-strided", "p3", "p16-l1300", "p47", "p784", "p64-strided"])
 def test_wide_fp32_matches_oracle(p, extra, l, r):
     n = 2500
     Xw = gaussian(n, p, seed=p, extra=extra)
