@@ -82,8 +82,6 @@ void free_model(Model& m) {
   if (m.base) model_release(m.dev, (size_t)m.bytes, m.base);
   delete[] m.idx_host;
   delete[] m.lam_host;
-  delete[] m.x1_host;
-  delete[] m.q_host;
   m = Model();
 }
 
@@ -404,15 +402,19 @@ mds_status mds_get_eigenvalues(const mds_model* h, double* lam) {
   return MDS_OK;
 }
 
+// X1 and q stay in the model's device memory; these getters copy them out
+// on request (the model is immutable, so no stream ordering is needed)
 mds_status mds_get_landmark_coords(const mds_model* h, double* X1) {
   if (!h || !X1) return set_error(MDS_ERR_INVALID_ARG, "NULL argument");
-  std::memcpy(X1, h->m.x1_host, sizeof(double) * h->m.l * h->m.r);
+  const hipError_t e = hipMemcpy(X1, h->m.x1_64, sizeof(double) * h->m.l * h->m.r, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "copy of the landmark coordinates");
   return MDS_OK;
 }
 
 mds_status mds_get_q(const mds_model* h, double* q) {
   if (!h || !q) return set_error(MDS_ERR_INVALID_ARG, "NULL argument");
-  std::memcpy(q, h->m.q_host, sizeof(double) * h->m.l);
+  const hipError_t e = hipMemcpy(q, h->m.q64, sizeof(double) * h->m.l, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "copy of q");
   return MDS_OK;
 }
 

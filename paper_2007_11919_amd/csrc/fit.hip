@@ -374,7 +374,6 @@ __global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ Vk, int
 // then X1 = V Lambda^{1/2} and W = 1/2 V Lambda^{-1/2} for live columns.
 __global__ __launch_bounds__(256) void k_finalize_cols(double* __restrict__ Vr, int64_t l, int r,
                                                        const double* __restrict__ lam,
-                                                       const int* __restrict__ live,
                                                        double* __restrict__ X1,
                                                        double* __restrict__ W64, int ldw,
                                                        float* __restrict__ W32t, int64_t l_pad) {
@@ -406,7 +405,8 @@ __global__ __launch_bounds__(256) void k_finalize_cols(double* __restrict__ Vr, 
     __syncthreads();
   }
   const double sgn = (Vr[shi[0] * r + tt] < 0.0) ? -1.0 : 1.0;
-  const bool on = live[tt] != 0;
+  // live direction: the same FP64 comparison the host makes for r_eff
+  const bool on = lam[tt] > MDS_TAU * lam[0];
   const double lt = lam[tt];
   const double sx = on ? sqrt(lt) : 0.0;
   const double sw = on ? 0.5 / sqrt(lt) : 0.0;
@@ -533,6 +533,19 @@ __global__ void k_copy_q(const double* __restrict__ q, int64_t l, int64_t l_pad,
   const double v = (i < l) ? q[i] : 0.0;
   q64[i] = v;
   q32[i] = (float)v;
+}
+
+// The host needs four small words after the fit: the two lo-part flags of
+// the split packs and the FP16 split scales.  They are gathered next to the
+// control words, so the fit ends with one small copy to the host.
+__global__ void k_stage_words(const int* __restrict__ lo_flags, const float* __restrict__ scales,
+                              int* __restrict__ stage) {
+  if (threadIdx.x == 0) {
+    stage[0] = lo_flags[0];
+    stage[1] = lo_flags[1];
+    stage[2] = __float_as_int(scales[0]);
+    stage[3] = __float_as_int(scales[1]);
+  }
 }
 
 // FP16 split scale: 2^s with the largest landmark magnitude at 2^12, so data
@@ -677,6 +690,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   const size_t oc64 = lay.take(sizeof(double) * l_pad);
   const size_t oq32 = lay.take(sizeof(float) * l_pad);
   const size_t oq64 = lay.take(sizeof(double) * l_pad);
+  const size_t ox1 = lay.take(sizeof(double) * (size_t)l * r);
   const size_t oa64 = lay.take(sizeof(double) * (size_t)r * p);
   const size_t oa32 = lay.take(sizeof(float) * (size_t)r * p);
   const size_t ob64 = lay.take(sizeof(double) * (size_t)r);
@@ -694,6 +708,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   m.c64 = b + oc64;
   m.q32 = b + oq32;
   m.q64 = b + oq64;
+  m.x1_64 = b + ox1;
   m.aff64 = b + oa64;
   m.aff32 = b + oa32;
   m.affb64 = b + ob64;
@@ -702,7 +717,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   MDS_HIP(hipMemsetAsync(m.base, 0, lay.off, st));
 
   // ---- scratch (stream-ordered, freed when the fit returns) ----
-  DevBuf bDQ, bV, bsmall, bS, bwork, bVr, bX1, bab;
+  DevBuf bDQ, bV, bsmall, bS, bwork, bVr, bab;
   MDS_HIP(hipMallocAsync(&bDQ.p, sizeof(double) * l * l, st));
   bDQ.st = st;
   MDS_HIP(hipMallocAsync(&bV.p, sizeof(double) * l * (kcap + 1), st));
@@ -715,8 +730,6 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   bwork.st = st;
   MDS_HIP(hipMallocAsync(&bVr.p, sizeof(double) * l * r, st));
   bVr.st = st;
-  MDS_HIP(hipMallocAsync(&bX1.p, sizeof(double) * l * r, st));
-  bX1.st = st;
   MDS_HIP(hipMallocAsync(&bab.p, sizeof(double) * ((size_t)2 * (kcap + 1) + 6 * MDS_MAX_R + 32), st));
   bab.st = st;
   double* DQ = (double*)bDQ.p;
@@ -732,7 +745,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   float* scales = reinterpret_cast<float*>(scal + 2);
   // ctrl: [0] stop, [1] stop step, [2] ok, [3] bad input, [4] asymmetric
   // input, [6] k of the last tridiagonal solve, [7] always 0 (no-stop view),
-  // [8] k of the newest-run solve, [10..11] lo flags of the split packs
+  // [8] k of the newest-run solve, [10..11] lo flags of the split packs,
+  // [16..19] the words read back at the end (lo flags, FP16 scales)
   int* ctrl = reinterpret_cast<int*>(scal + 8);
   double* alpha = (double*)bab.p;
   double* beta = alpha + (kcap + 1);
@@ -926,17 +940,11 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     LAUNCH_CHECK("ritz vectors");
   }
   if (!(htheta[0] > 0.0)) return set_error(MDS_ERR_DEGENERATE, "largest eigenvalue is not positive");
-  std::vector<int> live(r);
   int r_eff = 0;
-  for (int t = 0; t < r; ++t) {
-    live[t] = htheta[t] > MDS_TAU * htheta[0] ? 1 : 0;
-    r_eff += live[t];
-  }
+  for (int t = 0; t < r; ++t) r_eff += htheta[t] > MDS_TAU * htheta[0] ? 1 : 0;
   m.r_eff = r_eff;
-  int* live_dev = ctrl + 16;  // room for MDS_MAX_R ints after the control words
-  MDS_HIP(hipMemcpyAsync(live_dev, live.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
-  k_finalize_cols<<<r, 256, 0, st>>>((double*)bVr.p, l, r, theta, live_dev, (double*)bX1.p,
-                                     (double*)m.w64, ldw, (float*)m.w32, l_pad);
+  k_finalize_cols<<<r, 256, 0, st>>>((double*)bVr.p, l, r, theta, (double*)m.x1_64, (double*)m.w64,
+                                     ldw, (float*)m.w32, l_pad);
   k_copy_q<<<(unsigned)((l_pad + 255) / 256), 256, 0, st>>>(q, l, l_pad, (double*)m.q64,
                                                             (float*)m.q32);
   if (vectors) {
@@ -965,22 +973,19 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   } else {
     k_scale<<<1, 256, 0, st>>>(rowmax, 0, scales);  // unused without vectors
   }
+  int* words_dev = ctrl + 16;
+  k_stage_words<<<1, 64, 0, st>>>(ctrl + 10, scales, words_dev);
   LAUNCH_CHECK("finalise");
   // ---- host copies ----
   m.lam_host = new double[r];
-  m.x1_host = new double[(size_t)l * r];
-  m.q_host = new double[(size_t)l];
   for (int t = 0; t < r; ++t) m.lam_host[t] = htheta[t];
-  float hsc[2];
-  MDS_HIP(hipMemcpyAsync(m.x1_host, bX1.p, sizeof(double) * l * r, hipMemcpyDeviceToHost, st));
-  MDS_HIP(hipMemcpyAsync(m.q_host, q, sizeof(double) * l, hipMemcpyDeviceToHost, st));
-  MDS_HIP(hipMemcpyAsync(hctrl, ctrl, sizeof(hctrl), hipMemcpyDeviceToHost, st));
-  MDS_HIP(hipMemcpyAsync(hsc, scales, sizeof(hsc), hipMemcpyDeviceToHost, st));
+  int words[4];
+  MDS_HIP(hipMemcpyAsync(words, words_dev, sizeof(words), hipMemcpyDeviceToHost, st));
   MDS_HIP(hipStreamSynchronize(st));
-  m.bf_lo_zero = hctrl[10] ? 0 : 1;
-  m.h_lo_zero = hctrl[11] ? 0 : 1;
-  m.h_prescale = hsc[0];
-  m.h_postscale = hsc[1];
+  m.bf_lo_zero = words[0] ? 0 : 1;
+  m.h_lo_zero = words[1] ? 0 : 1;
+  std::memcpy(&m.h_prescale, &words[2], sizeof(float));
+  std::memcpy(&m.h_postscale, &words[3], sizeof(float));
   return MDS_OK;
 }
 

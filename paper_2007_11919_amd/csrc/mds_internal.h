@@ -83,13 +83,11 @@ struct Model {
   // host copies
   int64_t* idx_host = nullptr;
   double* lam_host = nullptr;   // r
-  double* x1_host = nullptr;    // l x r
-  double* q_host = nullptr;     // l
   // device buffers: one allocation (base), the rest point into it
   void* base = nullptr;
   void* m64 = nullptr;    // l_pad x nchunks64 x 16 doubles (FP64 operand and fit input)
   void* m32 = nullptr;    // round_up(l_pad, kSplitPackRows) x nchunks32 x 32 floats
-  void* mbf = nullptr;    // l_pad x nchunks32 x (32 hi + 32 lo) bf16
+  void* mbf = nullptr;    // round_up(l_pad, kSplitPackRows) x nchunks32 x (32 hi + 32 lo) bf16
   void* mh = nullptr;     // same for FP16 (scaled)
   void* w32 = nullptr;    // 16rb x l_pad float (column-major: output column, landmark)
   void* w64 = nullptr;    // l_pad x 16rb double
@@ -97,6 +95,7 @@ struct Model {
   void* c64 = nullptr;    // l_pad double
   void* q32 = nullptr;    // l_pad float: diag(Q1), for embedding from dissimilarities
   void* q64 = nullptr;    // l_pad double
+  void* x1_64 = nullptr;  // l x r double: landmark coordinates X1 (read by the getter)
   void* aff64 = nullptr;  // r x p double: A = 2 W' M of the affine form y = A x + b
   void* aff32 = nullptr;  // r x p float
   void* affb64 = nullptr; // r double: b = W' c
