@@ -1270,7 +1270,9 @@ hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int
     attr_set = true;
   }
   const int64_t ntiles = (n + BM - 1) / BM;
-  const int64_t cap = (int64_t)num_cu() * 64;
+  // persistent: one block per CU (the LDS holds one), each walking tiles
+  // gridDim apart; lane constants are computed (and spilled) once per block
+  const int64_t cap = (int64_t)num_cu();
   const int grid = (int)(ntiles < cap ? ntiles : cap);
   k_embed_wide<MODE, HI><<<grid, WTHREADS, WLDS_BYTES, st>>>(mv, reinterpret_cast<const float*>(X), n,
                                                              ldx, reinterpret_cast<float*>(Y), ldy);
