@@ -463,8 +463,10 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
 // 160 KB of LDS; 16-byte segments are XOR-swizzled by row instead of
 // padded, and the landmark operands are copied from memory straight into
 // LDS (the FP32 and split packs are allocated to a multiple of WBN rows,
-// zero past l_pad).  The row norms pass once through the buffer just
-// consumed.  The quarters are added in order at the end.  The landmark
+// zero past l_pad); in FP32, aligned data chunks without a ragged k-block
+// are copied the same way.  The split forms pass the row norms once through
+// the buffer just consumed; in FP32 each wave sums them from the operands
+// it reads.  The quarters are added in order at the end.  The landmark
 // order of the sums differs from the 128-landmark variant, so each model
 // and precision always runs the same variant (plain and serving launches
 // alike).
