@@ -271,6 +271,99 @@ __global__ __launch_bounds__(1024) void k_finish(double* __restrict__ V, int64_t
   }
 }
 
+// The same two Gram-Schmidt passes and the normalisation (k_dots, k_update
+// twice, then k_finish) in one block of 1024 threads, for a small basis:
+// w stays in LDS, wave g forms the dots of columns g, g + 16, ... (lanes
+// down the rows, fixed butterfly), and thread t updates rows t, t + 1024, ...
+// over the columns in order.  One launch per step instead of five.
+constexpr int kOrthThreads = 1024;
+constexpr int kOrthMaxL = 4096;           // w and the dots in the default 64 KB of LDS
+constexpr int64_t kOrthMaxBasis = 40000;  // (j + 1) l values of V read per pass
+__global__ __launch_bounds__(kOrthThreads) void k_orth(double* __restrict__ V, int64_t l, int j,
+                                                       const double* __restrict__ w_in,
+                                                       double* __restrict__ h1, double* __restrict__ h2,
+                                                       double* __restrict__ alpha,
+                                                       double* __restrict__ beta,
+                                                       const double* __restrict__ qnorm,
+                                                       int* __restrict__ ctrl, int write_next) {
+  if (ctrl[0]) return;
+  extern __shared__ double ws[];  // l values of w, then the j + 1 dots of each pass
+  __shared__ double red[kOrthThreads / 64];
+  double* hs = ws + l;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  constexpr int NW = kOrthThreads / 64;
+  const int nc = j + 1;
+  for (int64_t i = t; i < l; i += kOrthThreads) ws[i] = w_in[i];
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    double* h = pass == 0 ? h1 : h2;
+    double* hp = hs + pass * nc;
+    for (int c = wv; c < nc; c += NW) {
+      const double* vc = V + (int64_t)c * l;
+      // four independent sums (rows i, i + 64, i + 128, i + 192 mod 256),
+      // combined in a fixed order
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int64_t i = lane;
+      for (; i + 192 < l; i += 256) {
+        s0 = fma(vc[i], ws[i], s0);
+        s1 = fma(vc[i + 64], ws[i + 64], s1);
+        s2 = fma(vc[i + 128], ws[i + 128], s2);
+        s3 = fma(vc[i + 192], ws[i + 192], s3);
+      }
+      for (; i < l; i += 64) s0 = fma(vc[i], ws[i], s0);
+      double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) {
+        hp[c] = s;
+        h[c] = s;
+      }
+    }
+    __syncthreads();
+    for (int64_t i = t; i < l; i += kOrthThreads) {
+      // four independent sums over the columns (c mod 4), combined in order
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int c = 0;
+      for (; c + 3 < nc; c += 4) {
+        s0 = fma(V[(int64_t)c * l + i], hp[c], s0);
+        s1 = fma(V[(int64_t)(c + 1) * l + i], hp[c + 1], s1);
+        s2 = fma(V[(int64_t)(c + 2) * l + i], hp[c + 2], s2);
+        s3 = fma(V[(int64_t)(c + 3) * l + i], hp[c + 3], s3);
+      }
+      for (; c < nc; ++c) s0 = fma(V[(int64_t)c * l + i], hp[c], s0);
+      ws[i] -= (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
+  }
+  double s = 0.0;
+  for (int64_t i = t; i < l; i += kOrthThreads) s = fma(ws[i], ws[i], s);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  double tot = 0.0;
+#pragma unroll
+  for (int g = 0; g < NW; ++g) tot += red[g];
+  const double nrm = sqrt(tot);
+  const bool breakdown = !(nrm > 1e-12 * qnorm[0]);
+  if (t == 0) {
+    alpha[j] = hs[j] + hs[nc + j];  // first- and second-pass dots with v_j
+    beta[j] = breakdown ? 0.0 : nrm;
+  }
+  if (breakdown) {
+    if (t == 0) {
+      ctrl[0] = 1;
+      ctrl[1] = j;
+    }
+    return;
+  }
+  if (write_next) {
+    const double inv = 1.0 / nrm;
+    double* vn = V + (int64_t)(j + 1) * l;
+    for (int64_t i = t; i < l; i += kOrthThreads) vn[i] = ws[i] * inv;
+  }
+}
+
 // normalise w into column col (start vector or restart); ok[0] = success
 __global__ __launch_bounds__(1024) void k_set_column(double* __restrict__ V, int64_t l, int col,
                                                      const double* __restrict__ w, double min_norm,
@@ -813,6 +906,11 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     for (; j < jend; ++j) {
       const size_t shm = sizeof(double) * (size_t)(j + 1);
       k_symv<<<(unsigned)l, 256, 0, st>>>(DQ, l, Vk + (int64_t)j * l, w, ctrl);
+      if (l <= kOrthMaxL && (int64_t)(j + 1) * l <= kOrthMaxBasis) {
+        k_orth<<<1, kOrthThreads, sizeof(double) * (size_t)(l + 2 * (j + 1)), st>>>(
+            Vk, l, j, w, h1, h2, alpha, beta, scal + 1, ctrl, (j + 1 < kcap) ? 1 : 0);
+        continue;
+      }
       k_dots<<<j + 1, 256, 0, st>>>(Vk, l, w, h1, ctrl);
       k_update<<<upd_blocks, 256, shm, st>>>(Vk, l, j + 1, h1, w, ctrl);
       k_dots<<<j + 1, 256, 0, st>>>(Vk, l, w, h2, ctrl);
