@@ -73,7 +73,11 @@ __global__ __launch_bounds__(256) void k_mm_step(const TX* __restrict__ X, int64
   __shared__ double wv[4];
   __shared__ int64_t wi[4];
   const int t = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * MM_ROWS;
+  // odd steps walk the row blocks backwards, so each step starts on the rows
+  // the previous one read last (still in the memory-side cache when X is
+  // larger than it); a row's result does not depend on the order
+  const int64_t blk = (s & 1) ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x;
+  const int64_t row0 = blk * MM_ROWS;
   const int nrows = (int)((n - row0) < MM_ROWS ? (n - row0) : MM_ROWS);
   const TX* mrow = X + idx[s] * ldx;
   // thread t stages column t % 32, rows t / 32 + 8 u, of each 256 x 32
@@ -167,8 +171,8 @@ __global__ __launch_bounds__(256) void k_mm_step(const TX* __restrict__ X, int64
         best = wv[w];
         at = wi[w];
       }
-    bval[blockIdx.x] = best;
-    bidx[blockIdx.x] = at;
+    bval[blk] = best;
+    bidx[blk] = at;
   }
 }
 
