@@ -1230,18 +1230,6 @@ __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
 }
 
-int g_num_cu = 0;
-
-int num_cu() {
-  if (g_num_cu == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-    g_num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  }
-  return g_num_cu;
-}
 
 template <int MODE, typename TX, int RB>
 hipError_t launch_t(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
@@ -1300,6 +1288,19 @@ hipError_t launch_rb(const EmbedModelView& mv, const void* X, int64_t n, int64_t
 }
 
 }  // namespace
+
+static int g_num_cu = 0;
+
+int num_cu() {
+  if (g_num_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+    g_num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  }
+  return g_num_cu;
+}
 
 int embed_max_rb() { return 4; }
 

@@ -166,6 +166,8 @@ mds_status launch_embed_worklist(int mode, int rbc, const EmbedModelView* views_
                                  const TileWork* work_dev, const int32_t* nwork_dev,
                                  int grid, hipStream_t st);
 int embed_max_rb();
+// compute units of the current device (cached)
+int num_cu();
 int rb_class(int rb);
 int embed_class(int mode, int64_t p, int rb, int64_t l_pad, int m_lo_zero);
 int embed_blocks_per_cu(int mode, int rbc);

@@ -39,6 +39,22 @@ def test_maxmin_matches_oracle(name, make, l, first):
     assert np.array_equal(idx, ref), (idx[:10], ref[:10])
 
 
+@pytest.mark.parametrize("p,extra,n", [
+    (12, 0, 1000),    # 16-byte row loads, ragged chunk and ragged last block
+    (128, 0, 777),    # whole chunks only
+    (64, 4, 900),     # 16-byte aligned strided rows
+    (10, 0, 1000),    # p % 4 != 0: single-column loads
+    (132, 0, 700),    # a ragged fifth chunk
+], ids=["p12", "p128", "p64-strided", "p10", "p132"])
+def test_maxmin_fp32_layouts(p, extra, n):
+    """FP32 rows through both load paths of the MaxMin step (bit-exact indices)."""
+    rng = np.random.Generator(np.random.PCG64(p + n))
+    Xw = rng.standard_normal((n, p + extra)).astype(np.float32)
+    X = np.ascontiguousarray(Xw[:, :p])
+    idx = mds().maxmin_landmarks(dev(Xw)[:, :p], 30, 4)
+    assert np.array_equal(idx, opv.maxmin_landmarks(X.astype(np.float64), 30, 4))
+
+
 def test_maxmin_strided_and_duplicates():
     X = gen.small_gaussian(700, seed=5)
     wide = np.zeros((700, 13))
