@@ -489,8 +489,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rows would shard with one broadcast of the model; see the design notes). "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(rows would shard across GPUs after one broadcast of the model). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
