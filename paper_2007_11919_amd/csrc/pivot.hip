@@ -380,6 +380,90 @@ __global__ void k_t_mct(const double* __restrict__ T, const double* __restrict__
   K[e] = (i <= j) ? 0.5 * (a + b) : 0.5 * (b + a);
 }
 
+// ---- the p x p route (p < l): C'C = Mc S Mc' = B B' with B = Mc L and
+// S = L L' (Cholesky), so its nonzero eigenpairs are those of G = B'B
+// (p x p): eigenvalue lambda with vector w = B u / sqrt(lambda) for the unit
+// eigenvector u of G.  The dense solver then works on a p x p matrix (in
+// LDS for p <= 100 or so) instead of l x l.
+constexpr int PV_CHOL_MAXP = 128;
+// S = L L' in one block (right-looking, S in LDS); L lower triangular with
+// zeros above the diagonal.  flag[0] = 1 on a pivot that is not positive
+// and finite (S singular to working precision): the caller then takes the
+// l x l route.
+__global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ S, int p, double* __restrict__ L,
+                                               int* __restrict__ flag) {
+  extern __shared__ double a[];  // p x (p + 1)
+  const int t = threadIdx.x;
+  const int ld = p + 1;
+  for (int e = t; e < p * p; e += 1024) a[(e / p) * ld + e % p] = S[e];
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < p; ++k) {
+    const double d = a[k * ld + k];
+    if (!(d > 0.0) || !isfinite(d)) {
+      bad = true;
+      break;  // uniform: every thread reads the same pivot
+    }
+    const double piv = sqrt(d);
+    __syncthreads();  // every thread has read a[k][k]
+    for (int i = k + t; i < p; i += 1024) a[i * ld + k] = (i == k) ? piv : a[i * ld + k] / piv;
+    __syncthreads();
+    const int m = p - k - 1;  // trailing (m x m), lower part only
+    for (int e = t; e < m * m; e += 1024) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j <= i) a[i * ld + j] -= a[i * ld + k] * a[j * ld + k];
+    }
+    __syncthreads();
+  }
+  if (t == 0) flag[0] = bad ? 1 : 0;
+  if (bad) return;
+  for (int e = t; e < p * p; e += 1024) {
+    const int i = e / p, j = e % p;
+    L[e] = (j <= i) ? a[i * ld + j] : 0.0;
+  }
+}
+
+// B = Mc L (l x p), L lower triangular
+__global__ void k_mc_l(const double* __restrict__ Mc, const double* __restrict__ L, int64_t l, int64_t p,
+                       double* __restrict__ B) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= l * p) return;
+  const int64_t i = e / p, j = e % p;
+  double acc = 0.0;
+  for (int64_t q = j; q < p; ++q) acc = fma(Mc[i * p + q], L[q * p + j], acc);
+  B[e] = acc;
+}
+
+// G = B'B (p x p), computed identically for both entries of each pair
+__global__ void k_btb(const double* __restrict__ B, int64_t l, int64_t p, double* __restrict__ G) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= p * p) return;
+  const int64_t a = e / p, b = e % p;
+  const int64_t lo = a < b ? a : b, hi = a < b ? b : a;
+  double acc = 0.0;
+  for (int64_t i = 0; i < l; ++i) acc = fma(B[i * p + lo], B[i * p + hi], acc);
+  G[e] = acc;
+}
+
+// W[i][t] = sum_a B[i][a] U[a][t] / sqrt(lambda_t) (l x r; zero when
+// lambda_t <= 0: such a direction is dead)
+__global__ void k_w_from_u(const double* __restrict__ B, const double* __restrict__ U,
+                           const double* __restrict__ lam, int64_t l, int64_t p, int r,
+                           double* __restrict__ W) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= l * r) return;
+  const int64_t i = e / r;
+  const int t = (int)(e % r);
+  const double lt = lam[t];
+  if (!(lt > 0.0)) {
+    W[e] = 0.0;
+    return;
+  }
+  double acc = 0.0;
+  for (int64_t a2 = 0; a2 < p; ++a2) acc = fma(B[i * p + a2], U[a2 * r + t], acc);
+  W[e] = acc / sqrt(lt);
+}
+
 // A[t][k] = fac[t] * sum_j Mc[j][k] W[j][t] (r x p); b[t] = -sum_k A[t][k] xbar[k]
 __global__ void k_pivot_affine(const double* __restrict__ Mc, const double* __restrict__ W, int64_t l,
                                int64_t p, int r, const double* __restrict__ fac,
@@ -479,23 +563,67 @@ mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int
                                                                 S.get<double>());
     k_pivots_centred<TX><<<(unsigned)((p + 255) / 256), 256, 0, st>>>(X, ldx, p, idx.get<int64_t>(), l,
                                                                      Mc.get<double>());
+    PV_LAUNCH("pivot Gram matrices");
+  }
+  // l x l route: K = Mc S Mc' and its top eigenpairs
+  auto l_route = [&]() -> mds_status {
     k_mc_s<<<(unsigned)((l * p + 255) / 256), 256, 0, st>>>(Mc.get<double>(), S.get<double>(), l, p,
                                                            T.get<double>());
     k_t_mct<<<(unsigned)((l * l + 255) / 256), 256, 0, st>>>(T.get<double>(), Mc.get<double>(), l, p,
                                                             K.get<double>());
-    PV_LAUNCH("pivot Gram matrices");
+    PV_LAUNCH("pivot C'C");
+    return dense_top_eigen(K.get<double>(), (int)l, r, lam.get<double>(), W.get<double>(),
+                           stat.get<int>(), st);
+  };
+  // p x p route when p < l (see k_chol); cflag says whether it held
+  const bool p_route = p < l && p <= PV_CHOL_MAXP;
+  Buf Lc, Bm, G, U, cflag;
+  mds_status s = MDS_OK;
+  if (p_route) {
+    PV_HIP(alloc(Lc, sizeof(double) * p * p));
+    PV_HIP(alloc(Bm, sizeof(double) * l * p));
+    PV_HIP(alloc(G, sizeof(double) * p * p));
+    PV_HIP(alloc(U, sizeof(double) * p * r));
+    PV_HIP(alloc(cflag, sizeof(int)));
+    static bool chol_attr = false;
+    if (!chol_attr) {
+      PV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(sizeof(double) * PV_CHOL_MAXP * (PV_CHOL_MAXP + 1))));
+      chol_attr = true;
+    }
+    k_chol<<<1, 1024, sizeof(double) * (size_t)p * (p + 1), st>>>(S.get<double>(), (int)p, Lc.get<double>(),
+                                                                   cflag.get<int>());
+    k_mc_l<<<(unsigned)((l * p + 255) / 256), 256, 0, st>>>(Mc.get<double>(), Lc.get<double>(), l, p,
+                                                           Bm.get<double>());
+    k_btb<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(Bm.get<double>(), l, p, G.get<double>());
+    PV_LAUNCH("pivot p x p Gram");
+    s = dense_top_eigen(G.get<double>(), (int)p, r, lam.get<double>(), U.get<double>(), stat.get<int>(), st);
+    if (s != MDS_OK) return s;
+    k_w_from_u<<<(unsigned)((l * r + 255) / 256), 256, 0, st>>>(Bm.get<double>(), U.get<double>(),
+                                                               lam.get<double>(), l, p, r, W.get<double>());
+    PV_LAUNCH("pivot vectors");
+  } else {
+    s = l_route();
+    if (s != MDS_OK) return s;
   }
-  mds_status s = dense_top_eigen(K.get<double>(), (int)l, r, lam.get<double>(), W.get<double>(),
-                                 stat.get<int>(), st);
-  if (s != MDS_OK) return s;
   std::vector<double> th(r), hw((size_t)l * r);
-  int hstat = 0, hbad = 0;
+  int hstat = 0, hbad = 0, hchol = 0;
   PV_HIP(hipMemcpyAsync(th.data(), lam.p, sizeof(double) * r, hipMemcpyDeviceToHost, st));
   PV_HIP(hipMemcpyAsync(hw.data(), W.p, sizeof(double) * l * r, hipMemcpyDeviceToHost, st));
   PV_HIP(hipMemcpyAsync(&hstat, stat.p, sizeof(int), hipMemcpyDeviceToHost, st));
   PV_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (p_route) PV_HIP(hipMemcpyAsync(&hchol, cflag.p, sizeof(int), hipMemcpyDeviceToHost, st));
   PV_HIP(hipStreamSynchronize(st));
   if (hbad) return set_error(MDS_ERR_INVALID_ARG, "non-finite value in X");
+  if (p_route && hchol) {  // S singular to working precision: the l x l route
+    s = l_route();
+    if (s != MDS_OK) return s;
+    PV_HIP(hipMemcpyAsync(th.data(), lam.p, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+    PV_HIP(hipMemcpyAsync(hw.data(), W.p, sizeof(double) * l * r, hipMemcpyDeviceToHost, st));
+    PV_HIP(hipMemcpyAsync(&hstat, stat.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    PV_HIP(hipStreamSynchronize(st));
+  }
   if (hstat) return set_error(MDS_ERR_DEGENERATE, "largest eigenvalue is not positive");
   // sigma^2 = eigenvalues of C'C; lambda = sigma sqrt(n / l); column signs
   // from W (largest-|.| entry positive, first on ties)

@@ -68,6 +68,14 @@ def test_maxmin_strided_and_duplicates():
     assert ei.value.status == 4
 
 
+def constant_column(n, seed):
+    """Wide rows with one zero-variance column: the covariance is singular,
+    so its Cholesky factor does not exist and the l x l route is taken."""
+    X = gen.wide_gaussian(n, seed=seed).astype(np.float64)
+    X[:, 5] = 3.0
+    return X
+
+
 def compare_pivot(X, l, r, seed=0, idx=None, dtype=np.float64):
     Xs = X.astype(dtype)
     Y, lam, r_eff = mds().pivot_mds(dev(Xs), l, r, seed=seed, idx=idx)
@@ -83,7 +91,8 @@ def compare_pivot(X, l, r, seed=0, idx=None, dtype=np.float64):
 @pytest.mark.parametrize("name,make,l,r", [
     ("paper design, l=200", lambda: gen.paper_design(20000, 10, 2, seed=6), 200, 2),
     ("wide, eigen in LDS", lambda: gen.wide_gaussian(8000, seed=7).astype(np.float64), 80, 10),
-    ("wide, eigen in global memory", lambda: gen.wide_gaussian(8000, seed=8).astype(np.float64), 300, 10),
+    ("wide, p x p route", lambda: gen.wide_gaussian(8000, seed=8).astype(np.float64), 300, 10),
+    ("constant column: l x l route, eigen in global memory", lambda: constant_column(8000, 13), 300, 10),
     ("rank below r", lambda: gen.small_gaussian(2000, seed=9)[:, :3], 50, 5),
     ("all rows are pivots", lambda: gen.small_gaussian(150, seed=10), 150, 3),
 ], ids=lambda v: v if isinstance(v, str) else "")
