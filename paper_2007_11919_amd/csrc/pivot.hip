@@ -341,6 +341,101 @@ __global__ __launch_bounds__(256) void k_cov_part(const TX* __restrict__ X, int6
     }
 }
 
+// The same partial S for p <= 128 on the FP64 matrix cores.  The chunk is
+// walked 32 rows at a time: thread t owns column t % 128 of rows t / 128,
+// t / 128 + 2, ..., loads the next step's values into registers while the
+// matrix cores work on the current step, and writes them centred into LDS.
+// The 16 x 16 output tiles on and above the diagonal (T (T + 1) / 2 of them,
+// T = ceil(p / 16)) are shared out over the four waves, each accumulating
+// S[a][b] = sum_i x_ia x_ib with v_mfma_f64_16x16x4f64 (lane (i, q) holds
+// x[k + q][16 t + i] of both operands).  Every output is written to both
+// symmetric positions.
+constexpr int PV_COV_MAXP = 128;
+constexpr int PV_COV_ROWS = 32;
+constexpr int PV_COV_TILES = (PV_COV_MAXP / 16) * (PV_COV_MAXP / 16 + 1) / 2;  // 36
+constexpr int PV_COV_PER_WAVE = (PV_COV_TILES + 3) / 4;                       // 9
+template <typename TX>
+__global__ __launch_bounds__(256) void k_cov_mfma(const TX* __restrict__ X, int64_t ldx, int64_t n,
+                                                  int64_t p, const double* __restrict__ mean,
+                                                  int64_t rows_per, double* __restrict__ part) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NV = PV_COV_ROWS / 2;  // values a thread carries per step
+  __shared__ double xs[PV_COV_ROWS][PV_COV_MAXP + 1];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // the same in every lane of a wave
+  const int li = lane & 15, lq = lane >> 4;
+  const int T = (int)((p + 15) / 16);
+  const int npairs = T * (T + 1) / 2;
+  const int64_t c = blockIdx.x;
+  const int64_t i0 = c * rows_per, i1 = std::min(n, i0 + rows_per);
+  // the wave's tile pairs q = wv + 4 m, unranked row by row (ta <= tb)
+  int ta[PV_COV_PER_WAVE], tb[PV_COV_PER_WAVE];
+#pragma unroll
+  for (int m = 0; m < PV_COV_PER_WAVE; ++m) {
+    int q = wv + 4 * m, a = 0;
+    ta[m] = -1;
+    tb[m] = -1;
+    if (q < npairs) {
+      while (q >= T - a) {
+        q -= T - a;
+        ++a;
+      }
+      ta[m] = a;
+      tb[m] = a + q;
+    }
+  }
+  d4 acc[PV_COV_PER_WAVE];
+#pragma unroll
+  for (int m = 0; m < PV_COV_PER_WAVE; ++m) acc[m] = d4{0, 0, 0, 0};
+  const int cc = t & (PV_COV_MAXP - 1), r0 = t / PV_COV_MAXP;
+  const bool colok = cc < p;
+  const double mu = colok ? mean[cc] : 0.0;
+  TX v[NV];
+  auto fetch = [&](int64_t s0) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int64_t i = s0 + r0 + 2 * u;
+      v[u] = (colok && i < i1) ? X[i * ldx + cc] : TX(0);
+    }
+  };
+  fetch(i0);
+  for (int64_t s0 = i0; s0 < i1; s0 += PV_COV_ROWS) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int64_t i = s0 + r0 + 2 * u;
+      xs[r0 + 2 * u][cc] = (colok && i < i1) ? (double)v[u] - mu : 0.0;
+    }
+    __syncthreads();
+    if (s0 + PV_COV_ROWS < i1) fetch(s0 + PV_COV_ROWS);
+#pragma unroll
+    for (int k = 0; k < PV_COV_ROWS; k += 4) {
+#pragma unroll
+      for (int m = 0; m < PV_COV_PER_WAVE; ++m) {
+        if (ta[m] >= 0) {
+          const double av = xs[k + lq][16 * ta[m] + li];
+          const double bv = xs[k + lq][16 * tb[m] + li];
+          acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // FP64 result layout: element v of lane (j, g) is row g + 4 v, column j
+  double* Sp = part + c * p * p;
+#pragma unroll
+  for (int m = 0; m < PV_COV_PER_WAVE; ++m) {
+    if (ta[m] < 0) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t ra = 16 * ta[m] + lq + 4 * e, cb = 16 * tb[m] + li;
+      if (ra < p && cb < p) {
+        Sp[ra * p + cb] = acc[m][e];
+        Sp[cb * p + ra] = acc[m][e];
+      }
+    }
+  }
+}
+
 // Mc[j][k] = X[idx[j]][k] - mbar[k]; mbar = mean of the pivot rows (one
 // thread per column, pivots in the given order).
 template <typename TX>
@@ -520,9 +615,11 @@ template <typename TX>
 mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int64_t l, int r,
                      const int64_t* idx_host, double* Y, int64_t ldy, double* lam_host, int32_t* r_eff,
                      hipStream_t st) {
-  // row chunks: enough blocks to fill the device, partial S within ~512 MB
+  // row chunks of at least 1024 rows, partial S within ~512 MB; at most 768
+  // chunks, so the matrix-core covariance (three blocks per compute unit)
+  // covers all of them in one pass over 256 compute units
   const int64_t by_mem = std::max<int64_t>(1, ((int64_t)512 << 20) / (int64_t)(sizeof(double) * p * p));
-  const int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>({(n + 1023) / 1024, 1024, by_mem}));
+  const int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>({(n + 1023) / 1024, 768, by_mem}));
   const int64_t rows_per = (n + nchunks - 1) / nchunks;
   Buf idx, part, xbar, Spart, S, Mc, T, K, lam, W, stat, fac, A, b, bad, seg;
   auto alloc = [&](Buf& bb, size_t bytes) -> hipError_t {
@@ -556,7 +653,11 @@ mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int
                                                             xbar.get<double>());
     const unsigned tiles = (unsigned)((p + 63) / 64);
     dim3 gc(tiles, tiles, (unsigned)nchunks);
-    k_cov_part<TX><<<gc, 256, 0, st>>>(X, ldx, n, p, xbar.get<double>(), rows_per, Spart.get<double>());
+    if (p <= PV_COV_MAXP)
+      k_cov_mfma<TX><<<(unsigned)nchunks, 256, 0, st>>>(X, ldx, n, p, xbar.get<double>(), rows_per,
+                                                        Spart.get<double>());
+    else
+      k_cov_part<TX><<<gc, 256, 0, st>>>(X, ldx, n, p, xbar.get<double>(), rows_per, Spart.get<double>());
     dim3 gs2((unsigned)((p * p + 255) / 256), PSEG);
     k_sum_seg<<<gs2, 256, 0, st>>>(Spart.get<double>(), nchunks, p * p, seg.get<double>());
     k_sum_parts<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(seg.get<double>(), p * p, 1.0,

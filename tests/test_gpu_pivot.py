@@ -103,6 +103,20 @@ def test_pivot_matches_oracle(name, make, l, r):
         assert np.all(Y[:, 3:] == 0.0)
 
 
+@pytest.mark.parametrize("p,n,l,dtype", [
+    (17, 3001, 40, np.float64),    # one whole and one ragged 16-column tile; ragged row steps
+    (128, 5000, 60, np.float32),   # the largest p of the matrix-core covariance: 8 x 8 tiles
+    (129, 4000, 60, np.float64),   # the smallest p of the vector covariance kernel
+    (300, 4000, 350, np.float32),  # vector covariance over several 64 x 64 tiles
+], ids=["p17", "p128-fp32", "p129", "p300-fp32"])
+def test_pivot_covariance_shapes(p, n, l, dtype):
+    """Column counts on both sides of the covariance kernel choice."""
+    k = min(p, 10)
+    sig = np.concatenate([np.linspace(10.0, 2.0, k), np.ones(p - k)])
+    X = gen.gaussian_columns(n, sig, seed=p, dtype=dtype)
+    compare_pivot(X, l, 10, seed=1, dtype=dtype)
+
+
 def test_pivot_with_maxmin_pivots_and_fp32():
     X = gen.wide_gaussian(6000, seed=11)
     idx = mds().maxmin_landmarks(dev(X), 120, 0)
