@@ -430,6 +430,227 @@ __global__ __launch_bounds__(DC_NT) void k_dc_eigen(double* __restrict__ G, int 
   }
 }
 
+// ------------------------------------- register-resident eigensolver
+// The same reduction, tridiagonal solver and back-transformation for
+// d <= 16 NB, with the matrix held in registers instead of LDS: thread t
+// (row group g = t / 16, column group c = t % 16) keeps the NB x NB entries
+// A[g + 16 a][c + 16 b].  Row sums are butterflies over the 16 lanes of a
+// row group (the same bits in every lane), so a Householder step needs two
+// barriers; the Householder vector v_k replaces row k in the registers of
+// that row's lanes, which later steps leave unchanged.  LDS holds only the
+// tridiagonal matrix, the step vectors, Z and the inverse-iteration work,
+// so several parts run on one compute unit.
+constexpr int DCR_NT = 256;
+
+// all-reduce over the 16 lanes of a row group; every lane gets the same bits
+__device__ __forceinline__ double dcr_sum16(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return v;
+}
+
+// row ak of the register tile (ak is the same in every lane that asks)
+template <int NB>
+__device__ __forceinline__ void dcr_get_row(const double (&a)[NB][NB], int ak, double (&row)[NB]) {
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) row[bb] = 0.0;
+#pragma unroll
+  for (int aa = 0; aa < NB; ++aa)
+    if (aa == ak)
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) row[bb] = a[aa][bb];
+}
+
+template <int NB>
+__global__ __launch_bounds__(DCR_NT) void k_dc_eigen_reg(const double* __restrict__ G, int d, DcShape s,
+                                                       int rows_gram, int64_t j0, int nr,
+                                                       double* __restrict__ lam, double* __restrict__ U,
+                                                       double* __restrict__ Xs, int* __restrict__ status) {
+  constexpr int DM = 16 * NB;
+  extern __shared__ double dsm[];
+  __shared__ double vs[2][DM];  // v of the current step; p, or the back-transformation's second buffer
+  __shared__ double red[DCR_NT / 64];
+  __shared__ double theta[MDS_MAX_R];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int rg = 4 * wv + (lane >> 4), cg = lane & 15;
+  const int64_t jc = blockIdx.x, j = j0 + jc;
+  const int dd = rows_gram ? (int)dc_part_size(j, s) : d;
+  const int nrr = std::min(nr, dd);
+  const double* Gp = G + jc * (int64_t)d * d;
+  double* al = dsm;
+  double* be = al + d;
+  double* tau = be + d;
+  double* be2 = tau + d;
+  double* Z = be2 + d;
+  const int ldz = d;
+  double* wk = Z + (int64_t)nr * d;
+
+  double a[NB][NB];
+#pragma unroll
+  for (int aa = 0; aa < NB; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      const int i = rg + 16 * aa, jj = cg + 16 * bb;
+      a[aa][bb] = (i < dd && jj < dd) ? Gp[(int64_t)i * d + jj] : 0.0;
+    }
+
+  // Reduction to tridiagonal form, H_k = I - tau_k v v' with v_{k+1} = 1.
+  for (int k = 0; k + 2 < dd; ++k) {
+    if (rg == (k & 15)) {  // the 16 lanes holding row k
+      double row[NB];
+      dcr_get_row<NB>(a, k >> 4, row);
+      double x0 = 0.0, sg = 0.0, akk = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) {
+        const int jj = cg + 16 * bb;
+        if (jj == k) akk = row[bb];
+        if (jj == k + 1) x0 = row[bb];
+        if (jj >= k + 2 && jj < dd) sg = fma(row[bb], row[bb], sg);
+      }
+      akk = dcr_sum16(akk);  // one lane holds each of these two
+      x0 = dcr_sum16(x0);
+      sg = dcr_sum16(sg);
+      double tk = 0.0, beta = x0, scale = 0.0;
+      if (sg != 0.0) {
+        beta = -copysign(sqrt(x0 * x0 + sg), x0);
+        tk = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+      }
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) {
+        const int jj = cg + 16 * bb;
+        double v = 0.0;
+        if (sg != 0.0 && jj > k && jj < dd) v = (jj == k + 1) ? 1.0 : row[bb] * scale;
+        vs[0][jj] = v;
+        if (jj > k) row[bb] = v;  // v_k kept in row k for the back-transformation
+      }
+#pragma unroll
+      for (int aa = 0; aa < NB; ++aa)
+        if (aa == (k >> 4))
+#pragma unroll
+          for (int bb = 0; bb < NB; ++bb) a[aa][bb] = row[bb];
+      if (cg == 0) {
+        al[k] = akk;
+        be[k] = beta;
+        tau[k] = tk;
+      }
+    }
+    __syncthreads();
+    const double tk = tau[k];
+    if (tk == 0.0) continue;  // column k is already reduced: H_k = I
+    // p = tau A22 v, rows k + 1 .. dd - 1 (zero elsewhere)
+    double vr[NB], vc[NB], pr[NB];
+#pragma unroll
+    for (int aa = 0; aa < NB; ++aa) vr[aa] = vs[0][rg + 16 * aa];
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) vc[bb] = vs[0][cg + 16 * bb];
+    double pl = 0.0;
+#pragma unroll
+    for (int aa = 0; aa < NB; ++aa) {
+      double acc = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) acc = fma(a[aa][bb], vc[bb], acc);
+      acc = dcr_sum16(acc);
+      const int i = rg + 16 * aa;
+      pr[aa] = (i > k && i < dd) ? tk * acc : 0.0;
+      pl = fma(pr[aa], vr[aa], pl);
+    }
+    // p'v: the row groups of a wave, then the waves in order
+    pl += __shfl_xor(pl, 16, 64);
+    pl += __shfl_xor(pl, 32, 64);
+    if (lane == 0) red[wv] = pl;
+    if (cg == 0)
+#pragma unroll
+      for (int aa = 0; aa < NB; ++aa) vs[1][rg + 16 * aa] = pr[aa];
+    __syncthreads();
+    const double K = 0.5 * tk * (((red[0] + red[1]) + red[2]) + red[3]);
+    // A22 -= v w' + w v' with w = p - K v; both products rounded before the
+    // sum, so A[i][j] and A[j][i] stay the same bits
+    double wc[NB];
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) wc[bb] = fma(-K, vc[bb], vs[1][cg + 16 * bb]);
+#pragma unroll
+    for (int aa = 0; aa < NB; ++aa) {
+      const double wr = fma(-K, vr[aa], pr[aa]);
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb)
+        a[aa][bb] = a[aa][bb] - (__dmul_rn(vr[aa], wc[bb]) + __dmul_rn(wr, vc[bb]));
+    }
+  }
+  // the last 2 x 2 block
+#pragma unroll
+  for (int aa = 0; aa < NB; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      const int i = rg + 16 * aa, jj = cg + 16 * bb;
+      if (i == jj && i >= dd - 2 && i < dd) al[i] = a[aa][bb];
+      if (i == dd - 1 && jj == dd - 2) be[dd - 2] = a[aa][bb];
+    }
+  if (t == 0 && dd >= 2) tau[dd - 2] = 0.0;
+  __syncthreads();
+
+  tridiag_top<DCR_NT>(al, be, dd, nrr, theta, Z, ldz, wk, be2);
+  __syncthreads();
+
+  // back-transformation z <- H_k z, k descending: the lanes of row k post
+  // v_k, then row group g updates vectors g, g + 16, ...; the two buffers
+  // alternate over the reflections applied, so one barrier per reflection
+  int ph = 0;
+  for (int k = dd - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    double* vb = vs[ph];
+    ph ^= 1;
+    if (rg == (k & 15)) {
+      double row[NB];
+      dcr_get_row<NB>(a, k >> 4, row);
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) {
+        const int jj = cg + 16 * bb;
+        vb[jj] = (jj > k && jj < dd) ? row[bb] : 0.0;
+      }
+    }
+    __syncthreads();
+    double v[NB];
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) v[bb] = vb[cg + 16 * bb];
+    for (int tt = rg; tt < nrr; tt += 16) {
+      double* z = Z + (int64_t)tt * ldz;
+      double dot = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) {
+        const int jj = cg + 16 * bb;
+        if (jj < dd) dot = fma(v[bb], z[jj], dot);
+      }
+      const double f = tk * dcr_sum16(dot);
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) {
+        const int jj = cg + 16 * bb;
+        if (jj > k && jj < dd) z[jj] -= f * v[bb];
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int tt = t; tt < s.r; tt += DCR_NT) lam[j * s.r + tt] = tt < nrr ? theta[tt] : 0.0;
+  if (t == 0) status[j] = (nrr > 0 && theta[0] > 0.0) ? 0 : 1;
+  if (!rows_gram) {
+    for (int64_t e = t; e < (int64_t)dd * s.r; e += DCR_NT) {
+      const int i = (int)(e / s.r), tt = (int)(e % s.r);
+      U[(j * d + i) * s.r + tt] = tt < nrr ? Z[(int64_t)tt * ldz + i] : 0.0;
+    }
+  } else {
+    for (int64_t e = t; e < (int64_t)dd * s.r; e += DCR_NT) {
+      const int i = (int)(e / s.r), tt = (int)(e % s.r);
+      double v = 0.0;
+      if (tt < nrr && theta[tt] > 0.0) v = Z[(int64_t)tt * ldz + i] * sqrt(theta[tt]);
+      Xs[(j * s.m_max + i) * s.r + tt] = v;
+    }
+  }
+}
+
 // ---------------------------------------------- coordinates X_j = B u
 // Block: 64 rows of one part; features staged 32 at a time with U's rows.
 // Thread (row rl, group g) owns columns g, g+4, ..., in a fixed order.
@@ -693,6 +914,37 @@ size_t eigen_lds_bytes(int d, int nr) {
   return sizeof(double) * ((size_t)d * d + (5 + DC_NW) * (size_t)d + (size_t)nr * d + 4 * (size_t)d * nr);
 }
 
+// the register-resident solver: four vectors, Z and the inverse-iteration work
+constexpr int kDcRegMaxD = 112;
+size_t eigen_reg_lds_bytes(int d, int nr) {
+  return sizeof(double) * (size_t)d * (4 + 5 * (size_t)nr);
+}
+
+hipError_t set_eigen_reg_attrs() {
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax);
+  };
+  set(reinterpret_cast<const void*>(&k_dc_eigen_reg<1>));
+  set(reinterpret_cast<const void*>(&k_dc_eigen_reg<2>));
+  set(reinterpret_cast<const void*>(&k_dc_eigen_reg<4>));
+  set(reinterpret_cast<const void*>(&k_dc_eigen_reg<7>));
+  return e;
+}
+
+// tile width NB = ceil(d / 16), rounded up to 1, 2, 4 or 7
+void launch_eigen_reg(unsigned grid, size_t lds, hipStream_t st, const double* G, int d, DcShape s,
+                      int rows_gram, int64_t j0, int nr, double* lam, double* U, double* Xs, int* status) {
+  if (d <= 16)
+    k_dc_eigen_reg<1><<<grid, DCR_NT, lds, st>>>(G, d, s, rows_gram, j0, nr, lam, U, Xs, status);
+  else if (d <= 32)
+    k_dc_eigen_reg<2><<<grid, DCR_NT, lds, st>>>(G, d, s, rows_gram, j0, nr, lam, U, Xs, status);
+  else if (d <= 64)
+    k_dc_eigen_reg<4><<<grid, DCR_NT, lds, st>>>(G, d, s, rows_gram, j0, nr, lam, U, Xs, status);
+  else
+    k_dc_eigen_reg<7><<<grid, DCR_NT, lds, st>>>(G, d, s, rows_gram, j0, nr, lam, U, Xs, status);
+}
+
 template <typename TX>
 mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y, int64_t ldy,
                   double* lam_bar, int32_t* r_eff, int64_t* order_out, hipStream_t st) {
@@ -702,6 +954,7 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
   const int d = (int)(rows_gram ? s.m_max : p);
   const int nr = std::min(r, d);
   const bool in_lds = eigen_lds_bytes(d, nr) <= kDcLdsMax;
+  const bool in_regs = d <= kDcRegMaxD && eigen_reg_lds_bytes(d, nr) <= kDcLdsMax;
   const int64_t chunk =
       std::max<int64_t>(1, std::min<int64_t>(np, (int64_t)(kDcGramBudget / (sizeof(double) * (size_t)d * d))));
 
@@ -758,6 +1011,7 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
     DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_align),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
+    DC_HIP(set_eigen_reg_attrs());
     attr_set = true;
   }
   for (int64_t j0 = 0; j0 < np; j0 += chunk) {
@@ -769,7 +1023,11 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
     else
       k_dc_gram_feat<TX><<<ggrid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), j0, G.get<double>());
     DC_LAUNCH("part Gram matrices");
-    if (in_lds)
+    if (in_regs)
+      launch_eigen_reg((unsigned)cnt, eigen_reg_lds_bytes(d, nr), st, G.get<double>(), d, s,
+                       rows_gram ? 1 : 0, j0, nr, lam.get<double>(), U.get<double>(), Xs.get<double>(),
+                       status.get<int>());
+    else if (in_lds)
       k_dc_eigen<true><<<(unsigned)cnt, DC_NT, eigen_lds_bytes(d, nr), st>>>(
           G.get<double>(), d, s, rows_gram ? 1 : 0, j0, nr, nullptr, nullptr, nullptr,
           lam.get<double>(), U.get<double>(), Xs.get<double>(), status.get<int>());
