@@ -149,6 +149,102 @@ __global__ __launch_bounds__(256) void k_dc_gram_feat(const TX* __restrict__ X, 
     }
 }
 
+// The same B'B for p <= 128 on the FP64 matrix cores, one block per part.
+// The part's rows are walked 32 at a time through the partition order:
+// thread t owns column t % 128 of rows t / 128, t / 128 + 2, ..., loads the
+// next step's values into registers while the matrix cores work on the
+// current step, and writes them centred into LDS.  The 16 x 16 output tiles
+// on and above the diagonal are shared out over the four waves, each
+// accumulating G[a][b] = sum_i x_ia x_ib with v_mfma_f64_16x16x4f64 (lane
+// (i, q) holds x[k + q][16 t + i] of both operands); every output is
+// written to both symmetric positions, so G is exactly symmetric.
+constexpr int DCG_MAXP = 128;
+constexpr int DCG_ROWS = 32;
+constexpr int DCG_PER_WAVE = ((DCG_MAXP / 16) * (DCG_MAXP / 16 + 1) / 2 + 3) / 4;  // 9
+template <typename TX>
+__global__ __launch_bounds__(256) void k_dc_gram_mfma(const TX* __restrict__ X, int64_t ldx,
+                                                      const int64_t* __restrict__ order, DcShape s,
+                                                      const double* __restrict__ mean, int64_t j0,
+                                                      double* __restrict__ G) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NV = DCG_ROWS / 2;  // values a thread carries per step
+  __shared__ double xs[DCG_ROWS][DCG_MAXP + 1];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // the same in every lane of a wave
+  const int li = lane & 15, lq = lane >> 4;
+  const int64_t p = s.p;
+  const int T = (int)((p + 15) / 16);
+  const int npairs = T * (T + 1) / 2;
+  const int64_t jc = blockIdx.x, j = j0 + jc;
+  const int64_t m = dc_part_size(j, s);
+  // the wave's tile pairs q = wv + 4 u, unranked row by row (ta <= tb)
+  int ta[DCG_PER_WAVE], tb[DCG_PER_WAVE];
+#pragma unroll
+  for (int u = 0; u < DCG_PER_WAVE; ++u) {
+    int q = wv + 4 * u, a = 0;
+    ta[u] = -1;
+    tb[u] = -1;
+    if (q < npairs) {
+      while (q >= T - a) {
+        q -= T - a;
+        ++a;
+      }
+      ta[u] = a;
+      tb[u] = a + q;
+    }
+  }
+  d4 acc[DCG_PER_WAVE];
+#pragma unroll
+  for (int u = 0; u < DCG_PER_WAVE; ++u) acc[u] = d4{0, 0, 0, 0};
+  const int cc = t & (DCG_MAXP - 1), r0 = t / DCG_MAXP;
+  const bool colok = cc < p;
+  const double mu = colok ? mean[j * p + cc] : 0.0;
+  TX v[NV];
+  auto fetch = [&](int64_t s0) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int64_t i = s0 + r0 + 2 * u;
+      v[u] = (colok && i < m) ? X[order[dc_pos(j, i, s)] * ldx + cc] : TX(0);
+    }
+  };
+  fetch(0);
+  for (int64_t s0 = 0; s0 < m; s0 += DCG_ROWS) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int64_t i = s0 + r0 + 2 * u;
+      xs[r0 + 2 * u][cc] = (colok && i < m) ? (double)v[u] - mu : 0.0;
+    }
+    __syncthreads();
+    if (s0 + DCG_ROWS < m) fetch(s0 + DCG_ROWS);
+#pragma unroll
+    for (int k = 0; k < DCG_ROWS; k += 4) {
+#pragma unroll
+      for (int u = 0; u < DCG_PER_WAVE; ++u) {
+        if (ta[u] >= 0) {
+          const double av = xs[k + lq][16 * ta[u] + li];
+          const double bv = xs[k + lq][16 * tb[u] + li];
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // FP64 result layout: element e of lane (j, g) is row g + 4 e, column j
+  double* Gp = G + jc * p * p;
+#pragma unroll
+  for (int u = 0; u < DCG_PER_WAVE; ++u) {
+    if (ta[u] < 0) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t ra = 16 * ta[u] + lq + 4 * e, cb = 16 * tb[u] + li;
+      if (ra < p && cb < p) {
+        Gp[ra * p + cb] = acc[u][e];
+        Gp[cb * p + ra] = acc[u][e];
+      }
+    }
+  }
+}
+
 // B B' of a part (m x m, leading dimension m_max): G[i][i'] =
 // sum_k (x_ik - mu_k)(x_i'k - mu_k), features staged 16 at a time.
 template <typename TX>
@@ -442,12 +538,24 @@ __global__ __launch_bounds__(DC_NT) void k_dc_eigen(double* __restrict__ G, int 
 // so several parts run on one compute unit.
 constexpr int DCR_NT = 256;
 
-// all-reduce over the 16 lanes of a row group; every lane gets the same bits
+// v from another lane of the same 16-lane row, by a DPP move of both halves
+template <int CTRL>
+__device__ __forceinline__ double dcr_dpp(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// all-reduce over the 16 lanes of a row group: partner lanes 1 and 2 apart
+// (quad permutations), then the other quad of the half row and the other
+// half of the row (mirrors).  Each level adds the same two values in every
+// lane, so all 16 lanes get the same bits.
 __device__ __forceinline__ double dcr_sum16(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
+  v += dcr_dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dcr_dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dcr_dpp<0x141>(v);  // row_half_mirror
+  v += dcr_dpp<0x140>(v);  // row_mirror
   return v;
 }
 
@@ -1020,6 +1128,9 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
     dim3 ggrid(tiles, tiles, (unsigned)cnt);
     if (rows_gram)
       k_dc_gram_rows<TX><<<ggrid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), j0, G.get<double>());
+    else if (p <= DCG_MAXP)
+      k_dc_gram_mfma<TX><<<(unsigned)cnt, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), j0,
+                                                         G.get<double>());
     else
       k_dc_gram_feat<TX><<<ggrid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), j0, G.get<double>());
     DC_LAUNCH("part Gram matrices");
