@@ -572,13 +572,15 @@ __device__ __forceinline__ void dcr_get_row(const double (&a)[NB][NB], int ak, d
 }
 
 template <int NB>
-__global__ __launch_bounds__(DCR_NT) void k_dc_eigen_reg(const double* __restrict__ G, int d, DcShape s,
+__global__ __launch_bounds__(DCR_NT) __attribute__((amdgpu_waves_per_eu(3))) void k_dc_eigen_reg(double* __restrict__ G, int d, DcShape s,
                                                        int rows_gram, int64_t j0, int nr,
                                                        double* __restrict__ lam, double* __restrict__ U,
                                                        double* __restrict__ Xs, int* __restrict__ status) {
   constexpr int DM = 16 * NB;
   extern __shared__ double dsm[];
-  __shared__ double vs[2][DM];  // v of the current step; p, or the back-transformation's second buffer
+  // v of the step (two buffers alternating with k) and p; the first two
+  // also serve the back-transformation
+  __shared__ double vs[3][DM];
   __shared__ double red[DCR_NT / 64];
   __shared__ double theta[MDS_MAX_R];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -586,7 +588,7 @@ __global__ __launch_bounds__(DCR_NT) void k_dc_eigen_reg(const double* __restric
   const int64_t jc = blockIdx.x, j = j0 + jc;
   const int dd = rows_gram ? (int)dc_part_size(j, s) : d;
   const int nrr = std::min(nr, dd);
-  const double* Gp = G + jc * (int64_t)d * d;
+  double* Gp = G + jc * (int64_t)d * d;
   double* al = dsm;
   double* be = al + d;
   double* tau = be + d;
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(DCR_NT) void k_dc_eigen_reg(const double* __restric
         const int jj = cg + 16 * bb;
         double v = 0.0;
         if (sg != 0.0 && jj > k && jj < dd) v = (jj == k + 1) ? 1.0 : row[bb] * scale;
-        vs[0][jj] = v;
+        vs[k & 1][jj] = v;
         if (jj > k) row[bb] = v;  // v_k kept in row k for the back-transformation
       }
 #pragma unroll
@@ -651,9 +653,9 @@ __global__ __launch_bounds__(DCR_NT) void k_dc_eigen_reg(const double* __restric
     // p = tau A22 v, rows k + 1 .. dd - 1 (zero elsewhere)
     double vr[NB], vc[NB], pr[NB];
 #pragma unroll
-    for (int aa = 0; aa < NB; ++aa) vr[aa] = vs[0][rg + 16 * aa];
+    for (int aa = 0; aa < NB; ++aa) vr[aa] = vs[k & 1][rg + 16 * aa];
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb) vc[bb] = vs[0][cg + 16 * bb];
+    for (int bb = 0; bb < NB; ++bb) vc[bb] = vs[k & 1][cg + 16 * bb];
     double pl = 0.0;
 #pragma unroll
     for (int aa = 0; aa < NB; ++aa) {
@@ -671,20 +673,27 @@ __global__ __launch_bounds__(DCR_NT) void k_dc_eigen_reg(const double* __restric
     if (lane == 0) red[wv] = pl;
     if (cg == 0)
 #pragma unroll
-      for (int aa = 0; aa < NB; ++aa) vs[1][rg + 16 * aa] = pr[aa];
+      for (int aa = 0; aa < NB; ++aa) vs[2][rg + 16 * aa] = pr[aa];
     __syncthreads();
     const double K = 0.5 * tk * (((red[0] + red[1]) + red[2]) + red[3]);
     // A22 -= v w' + w v' with w = p - K v; both products rounded before the
-    // sum, so A[i][j] and A[j][i] stay the same bits
-    double wc[NB];
+    // sum, so A[i][j] and A[j][i] stay the same bits.  v and p are read
+    // again from LDS (the same values), which keeps them out of registers
+    // across the barrier.
+    const double* vk = vs[k & 1];
+    double vcb[NB], wc[NB];
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb) wc[bb] = fma(-K, vc[bb], vs[1][cg + 16 * bb]);
+    for (int bb = 0; bb < NB; ++bb) {
+      vcb[bb] = vk[cg + 16 * bb];
+      wc[bb] = fma(-K, vcb[bb], vs[2][cg + 16 * bb]);
+    }
 #pragma unroll
     for (int aa = 0; aa < NB; ++aa) {
-      const double wr = fma(-K, vr[aa], pr[aa]);
+      const double vra = vk[rg + 16 * aa];
+      const double wr = fma(-K, vra, vs[2][rg + 16 * aa]);
 #pragma unroll
       for (int bb = 0; bb < NB; ++bb)
-        a[aa][bb] = a[aa][bb] - (__dmul_rn(vr[aa], wc[bb]) + __dmul_rn(wr, vc[bb]));
+        a[aa][bb] = a[aa][bb] - (__dmul_rn(vra, wc[bb]) + __dmul_rn(wr, vcb[bb]));
     }
   }
   // the last 2 x 2 block
@@ -697,10 +706,28 @@ __global__ __launch_bounds__(DCR_NT) void k_dc_eigen_reg(const double* __restric
       if (i == dd - 1 && jj == dd - 2) be[dd - 2] = a[aa][bb];
     }
   if (t == 0 && dd >= 2) tau[dd - 2] = 0.0;
+  // the tile (now holding the reflectors) waits in this part's Gram slot,
+  // which nothing reads any more, while the tridiagonal solver runs: its
+  // registers are free for the solver
+#pragma unroll
+  for (int aa = 0; aa < NB; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      const int i = rg + 16 * aa, jj = cg + 16 * bb;
+      if (i < dd && jj < dd) Gp[(int64_t)i * d + jj] = a[aa][bb];
+    }
   __syncthreads();
 
   tridiag_top<DCR_NT>(al, be, dd, nrr, theta, Z, ldz, wk, be2);
   __syncthreads();
+  asm volatile("" ::: "memory");  // reload the tile from memory
+#pragma unroll
+  for (int aa = 0; aa < NB; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      const int i = rg + 16 * aa, jj = cg + 16 * bb;
+      a[aa][bb] = (i < dd && jj < dd) ? Gp[(int64_t)i * d + jj] : 0.0;
+    }
 
   // back-transformation z <- H_k z, k descending: the lanes of row k post
   // v_k, then row group g updates vectors g, g + 16, ...; the two buffers
@@ -1041,7 +1068,7 @@ hipError_t set_eigen_reg_attrs() {
 }
 
 // tile width NB = ceil(d / 16), rounded up to 1, 2, 4 or 7
-void launch_eigen_reg(unsigned grid, size_t lds, hipStream_t st, const double* G, int d, DcShape s,
+void launch_eigen_reg(unsigned grid, size_t lds, hipStream_t st, double* G, int d, DcShape s,
                       int rows_gram, int64_t j0, int nr, double* lam, double* U, double* Xs, int* status) {
   if (d <= 16)
     k_dc_eigen_reg<1><<<grid, DCR_NT, lds, st>>>(G, d, s, rows_gram, j0, nr, lam, U, Xs, status);
@@ -1208,9 +1235,12 @@ mds_status dense_top_eigen(double* G, int d, int r, double* lam, double* U, int*
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
     DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
+    DC_HIP(set_eigen_reg_attrs());
     attr_set = true;
   }
-  if (eigen_lds_bytes(d, nr) <= kDcLdsMax) {
+  if (d <= kDcRegMaxD && eigen_reg_lds_bytes(d, nr) <= kDcLdsMax) {
+    launch_eigen_reg(1, eigen_reg_lds_bytes(d, nr), st, G, d, s, 0, 0, nr, lam, U, nullptr, status);
+  } else if (eigen_lds_bytes(d, nr) <= kDcLdsMax) {
     k_dc_eigen<true><<<1, DC_NT, eigen_lds_bytes(d, nr), st>>>(G, d, s, 0, 0, nr, nullptr, nullptr,
                                                               nullptr, lam, U, nullptr, status);
   } else {

@@ -57,7 +57,7 @@ def run_and_compare(X, l, c, r, seed, parts=None, dtype=np.float64, ldx_pad=0, l
 
 CASES = [
     # (name, X builder, l, c, r)
-    ("c1 shape, feature Gram in LDS", lambda: gen.small_gaussian(5000, seed=11), 200, 10, 2),
+    ("c1 shape, feature Gram in registers", lambda: gen.small_gaussian(5000, seed=11), 200, 10, 2),
     ("paper design k=100 h=10", lambda: gen.paper_design(6000, 100, 10, seed=3), 400, 50, 10),
     ("row Gram in LDS (p > l)", lambda: gen.image_mixture(1500, p=300, seed=4).astype(np.float64), 120, 20, 5),
     ("row Gram in global memory", lambda: gen.image_mixture(1400, p=300, seed=5).astype(np.float64), 200, 20, 5),
