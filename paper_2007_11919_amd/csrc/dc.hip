@@ -788,53 +788,69 @@ __global__ __launch_bounds__(DCR_NT) __attribute__((amdgpu_waves_per_eu(3))) voi
 
 // ---------------------------------------------- coordinates X_j = B u
 // Block: 64 rows of one part; features staged 32 at a time with U's rows.
-// Thread (row rl, group g) owns columns g, g+4, ..., in a fixed order.
+// The four lanes 4 rl .. 4 rl + 3 share row rl: lane q takes features
+// 8 q .. 8 q + 7 of each chunk into up to 16 independent sums (one per
+// output column), and the quad adds its four partial sums in a fixed order
+// (the same bits in each lane).  Row addresses are looked up once.
 template <typename TX>
 __global__ __launch_bounds__(256) void k_dc_coords(const TX* __restrict__ X, int64_t ldx,
                                                    const int64_t* __restrict__ order, DcShape s,
                                                    const double* __restrict__ mean,
                                                    const double* __restrict__ U,
                                                    double* __restrict__ Xs) {
+  constexpr int RG = 16;  // output columns per pass
   __shared__ double Xt[64][33];
-  __shared__ double Ut[32][MDS_MAX_R + 1];
+  __shared__ double Ut[32][RG + 1];
   const int t = threadIdx.x;
-  const int rl = t & 63, g = t >> 6;
+  const int rl = t >> 2, q = t & 3;    // row of the block, quarter of each chunk
+  const int lr = t >> 5, lf = t & 31;  // staging: rows lr + 8 k, feature lf
   const int64_t j = blockIdx.y;
   const int64_t i0 = (int64_t)blockIdx.x * 64;
   const int64_t m = dc_part_size(j, s);
   if (i0 >= m) return;
   const double* mu = mean + j * s.p;
   const double* Uj = U + j * s.p * s.r;
-  double acc[MDS_MAX_R / 4];
+  const TX* xr[8];
 #pragma unroll
-  for (int u = 0; u < MDS_MAX_R / 4; ++u) acc[u] = 0.0;
-  for (int64_t f0 = 0; f0 < s.p; f0 += 32) {
-    for (int e = t; e < 64 * 32; e += 256) {
-      const int rr = e >> 5, ff = e & 31;
-      const int64_t i = i0 + rr, f = f0 + ff;
-      Xt[rr][ff] = (i < m && f < s.p) ? (double)X[order[dc_pos(j, i, s)] * ldx + f] - mu[f] : 0.0;
-    }
-    for (int e = t; e < 32 * s.r; e += 256) {
-      const int ff = e / s.r, tt = e % s.r;
-      Ut[ff][tt] = (f0 + ff < s.p) ? Uj[(f0 + ff) * s.r + tt] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < MDS_MAX_R / 4; ++u) {
-      const int tt = g + 4 * u;
-      if (tt < s.r) {
-        double a = acc[u];
-        for (int ff = 0; ff < 32; ++ff) a = fma(Xt[rl][ff], Ut[ff][tt], a);
-        acc[u] = a;
-      }
-    }
-    __syncthreads();
+  for (int k = 0; k < 8; ++k) {
+    const int64_t i = i0 + lr + 8 * k;
+    xr[k] = (i < m) ? X + order[dc_pos(j, i, s)] * ldx : nullptr;
   }
-  if (i0 + rl < m) {
+  for (int tt0 = 0; tt0 < s.r; tt0 += RG) {
+    double acc[RG];
 #pragma unroll
-    for (int u = 0; u < MDS_MAX_R / 4; ++u) {
-      const int tt = g + 4 * u;
-      if (tt < s.r) Xs[(j * s.m_max + i0 + rl) * s.r + tt] = acc[u];
+    for (int tt = 0; tt < RG; ++tt) acc[tt] = 0.0;
+    for (int64_t f0 = 0; f0 < s.p; f0 += 32) {
+      const int64_t f = f0 + lf;
+      const bool fin = f < s.p;
+      const double muf = fin ? mu[f] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) Xt[lr + 8 * k][lf] = (xr[k] && fin) ? (double)xr[k][f] - muf : 0.0;
+      for (int e = t; e < 32 * RG; e += 256) {
+        const int ff = e / RG, tt = e % RG;
+        Ut[ff][tt] = (f0 + ff < s.p && tt0 + tt < s.r) ? Uj[(f0 + ff) * s.r + tt0 + tt] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int ff = 8 * q + k;
+        const double xv = Xt[rl][ff];
+#pragma unroll
+        for (int tt = 0; tt < RG; ++tt) acc[tt] = fma(xv, Ut[ff][tt], acc[tt]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int tt = 0; tt < RG; ++tt) {
+      double v = acc[tt];
+      v += dcr_dpp<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+      v += dcr_dpp<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+      acc[tt] = v;
+    }
+    if (q == 0 && i0 + rl < m) {
+#pragma unroll
+      for (int tt = 0; tt < RG; ++tt)
+        if (tt0 + tt < s.r) Xs[(j * s.m_max + i0 + rl) * s.r + tt0 + tt] = acc[tt];
     }
   }
 }
