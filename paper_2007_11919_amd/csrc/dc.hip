@@ -547,6 +547,14 @@ __device__ __forceinline__ double dcr_dpp(double v) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// the value of the wave's first active lane, in every lane
+__device__ __forceinline__ double dcr_first(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // all-reduce over the 16 lanes of a row group: partner lanes 1 and 2 apart
 // (quad permutations), then the other quad of the half row and the other
 // half of the row (mirrors).  Each level adds the same two values in every
@@ -896,7 +904,8 @@ __global__ __launch_bounds__(256) void k_dc_signs(const double* __restrict__ Xs,
 // from k_dc_signs.
 // Part j >= 1: Procrustes fit on the c connecting rows over the r0 live
 // columns: C = (B - 1b')'(A - 1a') (B: part j, A: part 0), C = U S W' by
-// one-sided Jacobi (Hestenes) in one wave, T = U W', t = a - T' b; own rows
+// one-sided Jacobi (Hestenes) in one wave (column sums over the lanes as
+// DPP row sums when r0 <= 16), T = U W', t = a - T' b; own rows
 // become X_j T + t.  Columns r0..r-1 are zero.  status[j] = 2 when the
 // smallest singular value of C is <= 1e-9 of the largest.
 __global__ __launch_bounds__(256) void k_dc_align(const double* __restrict__ Xs,
@@ -962,11 +971,18 @@ __global__ __launch_bounds__(256) void k_dc_align(const double* __restrict__ Xs,
           const double x1 = own ? CS(b1, lane) : 0.0;
           const double x2 = own ? CS(b2, lane) : 0.0;
           double al = x1 * x1, be = x2 * x2, ga = x1 * x2;
+          if (r0 <= 16) {  // only the first 16 lanes hold values: DPP row sums,
+            // then lane 0's to every lane, so the control flow stays uniform
+            al = dcr_first(dcr_sum16(al));
+            be = dcr_first(dcr_sum16(be));
+            ga = dcr_first(dcr_sum16(ga));
+          } else {
 #pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            al += __shfl_xor(al, off, 64);
-            be += __shfl_xor(be, off, 64);
-            ga += __shfl_xor(ga, off, 64);
+            for (int off = 32; off > 0; off >>= 1) {
+              al += __shfl_xor(al, off, 64);
+              be += __shfl_xor(be, off, 64);
+              ga += __shfl_xor(ga, off, 64);
+            }
           }
           if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
           const double zeta = (be - al) / (2.0 * ga);
@@ -988,8 +1004,12 @@ __global__ __launch_bounds__(256) void k_dc_align(const double* __restrict__ Xs,
     for (int b = 0; b < r0; ++b) {
       const double x = own ? CS(b, lane) : 0.0;
       double nn = x * x;
+      if (r0 <= 16) {
+        nn = dcr_sum16(nn);
+      } else {
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
+        for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
+      }
       if (lane == 0) sig[b] = sqrt(nn);
     }
   }
