@@ -176,6 +176,102 @@ __global__ __launch_bounds__(256) void k_mm_step(const TX* __restrict__ X, int64
   }
 }
 
+// The same step on a column-major copy Xt of X (p rows of ldt values; ldt
+// a whole number of blocks): thread t of a block owns rows VE t .. VE t +
+// VE - 1 (one 16-byte load per column), so a step reads each column as one
+// contiguous run instead of 128-byte pieces of rows.  Per row the sum runs
+// over the columns in the same order with the same rounding as k_mm_step,
+// so the distances, and the landmarks, are the same.
+constexpr int MM_MAXP = 4096;
+template <typename TX>
+__global__ __launch_bounds__(256) void k_mm_transpose(const TX* __restrict__ X, int64_t ldx, int64_t n,
+                                                      int64_t p, TX* __restrict__ Xt, int64_t ldt) {
+  __shared__ TX tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;
+    tile[k][tx] = (r < n && c < p) ? X[r * ldx + c] : (TX)0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;
+    if (c < p) Xt[c * ldt + r] = tile[tx][k];
+  }
+}
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_mm_step_t(const TX* __restrict__ Xt, int64_t ldt, int64_t n,
+                                                   int64_t p, const TX* __restrict__ X, int64_t ldx,
+                                                   const int64_t* __restrict__ idx, int s,
+                                                   double* __restrict__ dmin, double* __restrict__ bval,
+                                                   int64_t* __restrict__ bidx) {
+  constexpr int VE = 16 / (int)sizeof(TX);  // rows per thread
+  constexpr int ROWS = 256 * VE;            // rows per block
+  typedef TX tv __attribute__((ext_vector_type(VE)));
+  __shared__ double ms[MM_MAXP];
+  __shared__ double wv[4];
+  __shared__ int64_t wi[4];
+  const int t = threadIdx.x;
+  // odd steps walk the row blocks backwards, as in k_mm_step
+  const int64_t blk = (s & 1) ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x;
+  const int64_t i0 = blk * ROWS + (int64_t)t * VE;
+  const TX* mrow = X + idx[s] * ldx;
+  for (int k = t; k < p; k += 256) ms[k] = (double)mrow[k];
+  __syncthreads();
+  double acc[VE];
+#pragma unroll
+  for (int e = 0; e < VE; ++e) acc[e] = 0.0;
+  const TX* col = Xt + i0;
+#pragma unroll 8
+  for (int64_t k = 0; k < p; ++k) {
+    const tv v = *reinterpret_cast<const tv*>(col + k * ldt);
+    const double m = ms[k];
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      const double d = (double)v[e] - m;
+      acc[e] = __dadd_rn(acc[e], __dmul_rn(d, d));
+    }
+  }
+  double best = -1.0;
+  int64_t at = INT64_MAX;
+#pragma unroll
+  for (int e = 0; e < VE; ++e) {
+    const int64_t i = i0 + e;
+    if (i < n) {
+      const double v = (s == 0) ? acc[e] : fmin(dmin[i], acc[e]);
+      dmin[i] = v;
+      if (v > best) {  // rows ascending: ties keep the smaller row
+        best = v;
+        at = i;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(best, off, 64);
+    const int64_t oi = __shfl_xor(at, off, 64);
+    if (ov > best || (ov == best && oi < at)) {
+      best = ov;
+      at = oi;
+    }
+  }
+  if ((t & 63) == 0) {
+    wv[t >> 6] = best;
+    wi[t >> 6] = at;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (wv[w] > best || (wv[w] == best && wi[w] < at)) {
+        best = wv[w];
+        at = wi[w];
+      }
+    bval[blk] = best;
+    bidx[blk] = at;
+  }
+}
+
 // merge the block results of step s - 1 into landmark s; flag[0] = 1 when
 // the largest smallest distance is zero (fewer than l distinct points)
 __global__ __launch_bounds__(256) void k_mm_pick(const double* __restrict__ bval,
@@ -596,10 +692,27 @@ mds_status maxmin_run(const TX* X, int64_t ldx, int64_t n, int64_t p, int64_t l,
   PV_HIP(alloc(flag, sizeof(int)));
   PV_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
   PV_HIP(hipMemcpyAsync(idx.p, &first, sizeof(int64_t), hipMemcpyHostToDevice, st));
+  // column-major copy when there is room for it (else the row-major steps)
+  constexpr int64_t ROWS_T = 256 * (16 / (int64_t)sizeof(TX));
+  const int64_t ldt = (n + ROWS_T - 1) / ROWS_T * ROWS_T;
+  const int nbt = (int)(ldt / ROWS_T);  // <= nb
+  Buf Xt;
+  bool col_major = l > 1 && p <= MM_MAXP && alloc(Xt, sizeof(TX) * p * ldt) == hipSuccess;
+  if (!col_major) (void)hipGetLastError();
+  if (col_major) {
+    k_mm_transpose<TX><<<dim3((unsigned)(ldt / 32), (unsigned)((p + 31) / 32)), 256, 0, st>>>(
+        X, ldx, n, p, Xt.get<TX>(), ldt);
+    PV_LAUNCH("maxmin column-major copy");
+  }
+  const int nbs = col_major ? nbt : nb;
   for (int s = 0; s + 1 < l; ++s) {
-    k_mm_step<TX><<<nb, 256, 0, st>>>(X, ldx, n, p, idx.get<int64_t>(), s, dmin.get<double>(),
-                                      bval.get<double>(), bidx.get<int64_t>());
-    k_mm_pick<<<1, 256, 0, st>>>(bval.get<double>(), bidx.get<int64_t>(), nb, idx.get<int64_t>(), s + 1,
+    if (col_major)
+      k_mm_step_t<TX><<<nbs, 256, 0, st>>>(Xt.get<TX>(), ldt, n, p, X, ldx, idx.get<int64_t>(), s,
+                                           dmin.get<double>(), bval.get<double>(), bidx.get<int64_t>());
+    else
+      k_mm_step<TX><<<nbs, 256, 0, st>>>(X, ldx, n, p, idx.get<int64_t>(), s, dmin.get<double>(),
+                                         bval.get<double>(), bidx.get<int64_t>());
+    k_mm_pick<<<1, 256, 0, st>>>(bval.get<double>(), bidx.get<int64_t>(), nbs, idx.get<int64_t>(), s + 1,
                                  flag.get<int>());
   }
   PV_LAUNCH("maxmin steps");
