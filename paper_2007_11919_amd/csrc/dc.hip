@@ -68,24 +68,33 @@ __global__ void k_dc_keys(int64_t n, uint64_t seed, uint64_t* __restrict__ keys,
 }
 
 // ----------------------------------------------------------- part means
-// mean[j][k] over the rows of part j, in row order; flags non-finite input.
+// mean[j][k] over the rows of part j: a block takes 64 columns, wave g the
+// rows i = g (mod 4) in order, and the four partial sums are added in a
+// fixed order; flags non-finite input.
 template <typename TX>
 __global__ __launch_bounds__(256) void k_dc_mean(const TX* __restrict__ X, int64_t ldx,
                                                  const int64_t* __restrict__ order, DcShape s,
                                                  double* __restrict__ mean, int* __restrict__ bad) {
+  __shared__ double part[4][64];
+  const int t = threadIdx.x, kk = t & 63, g = t >> 6;
   const int64_t j = blockIdx.x;
-  const int64_t k = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  if (k >= s.p) return;
+  const int64_t k = (int64_t)blockIdx.y * 64 + kk;
   const int64_t m = dc_part_size(j, s);
   double acc = 0.0;
   bool fin = true;
-  for (int64_t i = 0; i < m; ++i) {
-    const double v = (double)X[order[dc_pos(j, i, s)] * ldx + k];
-    fin = fin && isfinite(v);
-    acc += v;
+  if (k < s.p) {
+#pragma unroll 4
+    for (int64_t i = g; i < m; i += 4) {
+      const double v = (double)X[order[dc_pos(j, i, s)] * ldx + k];
+      fin = fin && isfinite(v);
+      acc += v;
+    }
   }
-  mean[j * s.p + k] = acc / (double)m;
+  part[g][kk] = acc;
   if (!fin) bad[0] = 1;
+  __syncthreads();
+  if (g == 0 && k < s.p)
+    mean[j * s.p + k] = (((part[0][kk] + part[1][kk]) + part[2][kk]) + part[3][kk]) / (double)m;
 }
 
 // -------------------------------------------------------- Gram matrices
@@ -1170,7 +1179,7 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
                                      vals.get<int64_t>(), order, (size_t)n, 0, 64, st));
   }
   {
-    dim3 grid((unsigned)np, (unsigned)((p + 255) / 256));
+    dim3 grid((unsigned)np, (unsigned)((p + 63) / 64));
     k_dc_mean<TX><<<grid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), bad.get<int>());
     DC_LAUNCH("part means");
   }

@@ -64,6 +64,7 @@ CASES = [
     ("row Gram in registers (l <= 112)", lambda: gen.image_mixture(1300, p=300, seed=12).astype(np.float64), 100, 20, 6),
     ("feature Gram in registers, p = 112", lambda: gen.paper_design(4000, 112, 10, seed=13), 300, 40, 10),
     ("feature Gram in registers, p = 40", lambda: gen.paper_design(3000, 40, 5, seed=14), 200, 30, 5),
+    ("feature Gram in registers, p = 24", lambda: gen.paper_design(2500, 24, 4, seed=15), 150, 20, 4),
     ("feature Gram in global memory", lambda: gen.paper_design(3000, 150, 4, seed=6), 400, 20, 4),
     ("one part (n <= l)", lambda: gen.small_gaussian(150, seed=7), 200, 10, 3),
     ("last part one own row", lambda: gen.small_gaussian(1 + 30 + 7 * 90, seed=8), 120, 30, 3),

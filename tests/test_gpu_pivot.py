@@ -91,6 +91,7 @@ def compare_pivot(X, l, r, seed=0, idx=None, dtype=np.float64):
 @pytest.mark.parametrize("name,make,l,r", [
     ("paper design, l=200", lambda: gen.paper_design(20000, 10, 2, seed=6), 200, 2),
     ("wide, l x l route, eigen in registers", lambda: gen.wide_gaussian(8000, seed=7).astype(np.float64), 80, 10),
+    ("wide, l x l route, l = 30", lambda: gen.wide_gaussian(6000, seed=17).astype(np.float64), 30, 8),
     ("wide, p x p route", lambda: gen.wide_gaussian(8000, seed=8).astype(np.float64), 300, 10),
     ("constant column: l x l route, eigen in global memory", lambda: constant_column(8000, 13), 300, 10),
     ("rank below r", lambda: gen.small_gaussian(2000, seed=9)[:, :3], 50, 5),
