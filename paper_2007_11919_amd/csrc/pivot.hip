@@ -532,17 +532,28 @@ __global__ __launch_bounds__(256) void k_cov_mfma(const TX* __restrict__ X, int6
   }
 }
 
-// Mc[j][k] = X[idx[j]][k] - mbar[k]; mbar = mean of the pivot rows (one
-// thread per column, pivots in the given order).
+// Mc[j][k] = X[idx[j]][k] - mbar[k]; mbar = mean of the pivot rows: a block
+// takes 64 columns, wave g the pivots j = g (mod 4) in order, and the four
+// partial sums are added in a fixed order.
 template <typename TX>
-__global__ void k_pivots_centred(const TX* __restrict__ X, int64_t ldx, int64_t p,
-                                 const int64_t* __restrict__ idx, int64_t l, double* __restrict__ Mc) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= p) return;
+__global__ __launch_bounds__(256) void k_pivots_centred(const TX* __restrict__ X, int64_t ldx, int64_t p,
+                                                        const int64_t* __restrict__ idx, int64_t l,
+                                                        double* __restrict__ Mc) {
+  __shared__ double ws[4][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
   double acc = 0.0;
-  for (int64_t j = 0; j < l; ++j) acc += (double)X[idx[j] * ldx + k];
-  const double mb = acc / (double)l;
-  for (int64_t j = 0; j < l; ++j) Mc[j * p + k] = (double)X[idx[j] * ldx + k] - mb;
+  if (k < p) {
+#pragma unroll 4
+    for (int64_t j = g; j < l; j += 4) acc += (double)X[idx[j] * ldx + k];
+  }
+  ws[g][lane] = acc;
+  __syncthreads();
+  const double mb = (((ws[0][lane] + ws[1][lane]) + ws[2][lane]) + ws[3][lane]) / (double)l;
+  if (k < p) {
+#pragma unroll 4
+    for (int64_t j = g; j < l; j += 4) Mc[j * p + k] = (double)X[idx[j] * ldx + k] - mb;
+  }
 }
 
 // T = Mc S (l x p), one output per thread
@@ -775,8 +786,8 @@ mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int
     k_sum_seg<<<gs2, 256, 0, st>>>(Spart.get<double>(), nchunks, p * p, seg.get<double>());
     k_sum_parts<<<(unsigned)((p * p + 255) / 256), 256, 0, st>>>(seg.get<double>(), p * p, 1.0,
                                                                 S.get<double>());
-    k_pivots_centred<TX><<<(unsigned)((p + 255) / 256), 256, 0, st>>>(X, ldx, p, idx.get<int64_t>(), l,
-                                                                     Mc.get<double>());
+    k_pivots_centred<TX><<<(unsigned)((p + 63) / 64), 256, 0, st>>>(X, ldx, p, idx.get<int64_t>(), l,
+                                                                    Mc.get<double>());
     PV_LAUNCH("pivot Gram matrices");
   }
   // l x l route: K = Mc S Mc' and its top eigenpairs
