@@ -610,10 +610,12 @@ __global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ S, int
     __syncthreads();  // every thread has read a[k][k]
     for (int i = k + t; i < p; i += 1024) a[i * ld + k] = (i == k) ? piv : a[i * ld + k] / piv;
     __syncthreads();
-    const int m = p - k - 1;  // trailing (m x m), lower part only
-    for (int e = t; e < m * m; e += 1024) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j <= i) a[i * ld + j] -= a[i * ld + k] * a[j * ld + k];
+    // trailing lower part: thread (ti, tj) of a 32 x 32 grid takes rows
+    // k + 1 + ti + 32 u and columns k + 1 + tj + 32 v up to the diagonal
+    const int ti = t >> 5, tj = t & 31;
+    for (int i = k + 1 + ti; i < p; i += 32) {
+      const double lik = a[i * ld + k];
+      for (int j = k + 1 + tj; j <= i; j += 32) a[i * ld + j] -= lik * a[j * ld + k];
     }
     __syncthreads();
   }
