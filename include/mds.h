@@ -166,9 +166,11 @@ mds_status mds_maxmin_landmarks(const void* X, int32_t dt, int64_t n, int64_t p,
  * lambda_k = sigma_k sqrt(n / l) estimates Q's eigenvalues (exact when the
  * pivots are all the rows) and Y = U_r Lambda_r^{1/2}.  The sign of column
  * k follows W's column k (largest-|.| entry positive, first pivot on ties);
- * direction k is live when sigma_k^2 > MDS_TAU * sigma_1^2 (the eigenvalue
- * test on C'C, whose eigenvalues are computed); dead columns are zero and
- * report lambda = 0.  Dissimilarities
+ * direction k is live when sigma_k^2 > MDS_TAU * sigma_1^2: the rule of
+ * Section 2 (keep eigenvalues above MDS_TAU times the largest) applied to
+ * the matrix pivot MDS decomposes, C'C, whose eigenvalues are sigma^2 (so
+ * lambda_k > sqrt(MDS_TAU) lambda_1); dead columns are zero and report
+ * lambda = 0.  Dissimilarities
  * are squared Euclidean distances, for which C = Xc Mc' (rows and pivots
  * centred on their means); the work is computed through that identity in
  * FP64 (means, p x p cross-product, l x l eigenproblem, one streaming pass).
@@ -298,11 +300,15 @@ mds_status mds_serve_create(int64_t budget_bytes, int32_t max_slots, int32_t til
  * m alive until mds_serve_destroy.  Errors: BUDGET if it does not fit. */
 mds_status mds_serve_add_model(mds_server* s, const mds_model* m, int32_t* model_id);
 /* Queue an embed request (non-blocking).  X, Y as for mds_embed (device,
- * caller-owned, must stay valid until the ticket completes); prec is
- * MDS_PREC_FP32 or MDS_PREC_SPLIT_BF16 / _FP16.  Errors: BUDGET if the
- * request alone exceeds the budget left after the models. */
-mds_status mds_serve_submit(mds_server* s, int32_t model_id, const void* X, int64_t n_pts,
-                            int64_t ldx, int32_t prec, void* Y, int64_t ldy, int64_t* ticket);
+ * caller-owned, must stay valid until the ticket completes): X holds n_pts
+ * rows of the model's p values, dt must be MDS_F32; Y holds n_pts rows of
+ * at least r floats.  prec is MDS_PREC_FP32 or MDS_PREC_SPLIT_BF16 / _FP16.
+ * Errors: INVALID_ARG (dt other than MDS_F32, prec, NULL pointers,
+ * ldx < p, ldy < r), NOT_FOUND (model id), BUDGET if the request alone
+ * exceeds the budget left after the models. */
+mds_status mds_serve_submit(mds_server* s, int32_t model_id, const void* X, int32_t dt,
+                            int64_t n_pts, int64_t ldx, int32_t prec, void* Y, int64_t ldy,
+                            int64_t* ticket);
 /* Ticket state: 0 queued, 1 admitted, 2 done.  Times are seconds on the
  * server's monotonic clock; any output pointer may be NULL. */
 mds_status mds_serve_poll(mds_server* s, int64_t ticket, int32_t* state, double* t_submit,

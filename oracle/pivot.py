@@ -19,7 +19,17 @@ infrastructure only; nothing on the product path may import it).
   exact when the pivots are all the points (C = Q); the configuration is
   X = U_r Lambda_r^{1/2}; the sign of each column follows the right
   singular vector in pivot space (largest-magnitude entry positive, first
-  on ties); columns with lambda <= TAU lambda_1 are zero.
+  on ties).
+* Live directions.  Classical MDS (Section 2, step 3) keeps the r greatest
+  non-negative eigenvalues of the matrix it decomposes; the reading used for
+  every method here is "eigenvalue > TAU times the largest".  Pivot MDS
+  decomposes C through its singular value decomposition, i.e. the
+  eigendecomposition of C'C (right singular vectors = its eigenvectors,
+  squared singular values = its eigenvalues), so the rule applies to
+  sigma_k^2: direction k is live when sigma_k^2 > TAU sigma_1^2.  The
+  estimate lambda = sigma sqrt(n / l) only rescales what was decomposed.
+  In terms of lambda this is lambda_k > sqrt(TAU) lambda_1; dead columns
+  are zero and report lambda = 0.
 """
 
 import numpy as np
@@ -84,7 +94,7 @@ def pivot_mds(X, idx, r):
     lam = s * np.sqrt(n / l)
     if not lam[0] > 0:
         raise DegenerateError("largest eigenvalue is not positive")
-    live = s * s > TAU * s[0] * s[0]
+    live = s * s > TAU * s[0] * s[0]  # eigenvalues of C'C (module docstring)
     lam = np.where(live, lam, 0.0)
     Y = np.zeros((n, len(lam)))
     Y[:, live] = U[:, live] * np.sqrt(lam[live])

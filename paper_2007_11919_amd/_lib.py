@@ -47,7 +47,7 @@ SIGNATURES = {
     "mds_last_hip_error": (c_i32, []),
     "mds_serve_create": (c_i32, [c_i64, c_i32, c_i32, ctypes.POINTER(c_vp)]),
     "mds_serve_add_model": (c_i32, [c_vp, c_vp, P_i32]),
-    "mds_serve_submit": (c_i32, [c_vp, c_i32, c_vp, c_i64, c_i64, c_i32, c_vp, c_i64, P_i64]),
+    "mds_serve_submit": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_i64, c_i64, c_i32, c_vp, c_i64, P_i64]),
     "mds_serve_poll": (c_i32, [c_vp, c_i64, P_i32, P_dbl, P_dbl, P_dbl]),
     "mds_serve_wait": (c_i32, [c_vp, c_i64, c_dbl]),
     "mds_serve_stats": (c_i32, [c_vp, ctypes.POINTER(ServeStats)]),

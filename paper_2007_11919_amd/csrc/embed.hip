@@ -13,9 +13,13 @@
 // row (double-buffered, one barrier per chunk):
 //   FP32        32 values, v_mfma_f32_16x16x4_f32
 //   FP64        16 values, v_mfma_f64_16x16x4_f64
-//   split BF16  32 hi + 32 lo values, v_mfma_f32_16x16x32_bf16, three
-//               products hi.hi + hi.lo + lo.hi with FP32 accumulation
-//   split FP16  the same with FP16 operands scaled by a power of two
+//   split BF16  32 hi + 32 lo values, v_mfma_f32_16x16x32_bf16, four
+//               products hi.hi + lo.hi + hi.lo + lo.lo with FP32
+//               accumulation (a BF16 part carries 8 bits, so the lo.lo
+//               term is 2^-16 of x.m, the order of what the split leaves
+//               out, and worth keeping)
+//   split FP16  hi.hi + lo.hi + hi.lo with FP16 operands scaled by a power
+//               of two (11-bit parts: lo.lo is 2^-22 of x.m, dropped)
 // The MFMA computes S^T (landmarks x rows), so its accumulator is directly
 // the B operand of the projection MFMA Y^T += W^T E^T (no data movement);
 // the epilogue e = c - |x|^2 + 2 S runs in between on the accumulator.
@@ -313,6 +317,8 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
             if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
             if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+            if (do_mlo && do_xlo)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl[j], acc[i][j], 0, 0, 0);
           } else {
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
             if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
@@ -717,6 +723,8 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
           if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
           if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+          if (do_mlo && do_xlo)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl[j], acc[i][j], 0, 0, 0);
         } else {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
           if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);

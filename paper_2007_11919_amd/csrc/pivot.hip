@@ -590,8 +590,8 @@ __global__ void k_t_mct(const double* __restrict__ T, const double* __restrict__
 constexpr int PV_CHOL_MAXP = 128;
 // S = L L' in one block (right-looking, S in LDS); L lower triangular with
 // zeros above the diagonal.  flag[0] = 1 on a pivot that is not positive
-// and finite (S singular to working precision): the caller then takes the
-// l x l route.
+// and finite (S singular to working precision): L is then zero and the
+// caller takes the l x l route.
 __global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ S, int p, double* __restrict__ L,
                                                int* __restrict__ flag) {
   extern __shared__ double a[];  // p x (p + 1)
@@ -620,10 +620,11 @@ __global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ S, int
     __syncthreads();
   }
   if (t == 0) flag[0] = bad ? 1 : 0;
-  if (bad) return;
+  // on failure L is all zeros, so the p x p chain launched behind this
+  // kernel (before the host reads the flag) works on defined values
   for (int e = t; e < p * p; e += 1024) {
     const int i = e / p, j = e % p;
-    L[e] = (j <= i) ? a[i * ld + j] : 0.0;
+    L[e] = (!bad && j <= i) ? a[i * ld + j] : 0.0;
   }
 }
 
@@ -854,8 +855,9 @@ mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int
   if (hstat) return set_error(MDS_ERR_DEGENERATE, "largest eigenvalue is not positive");
   // sigma^2 = eigenvalues of C'C; lambda = sigma sqrt(n / l); column signs
   // from W (largest-|.| entry positive, first on ties)
-  // a direction is live when sigma^2 > TAU sigma_1^2 (the eigenvalue test
-  // on C'C itself); dead directions report lambda = 0
+  // a direction is live when sigma^2 > TAU sigma_1^2: Section 2's test on
+  // the eigenvalues of the matrix pivot MDS decomposes, C'C; dead directions
+  // report lambda = 0
   std::vector<double> hfac(r, 0.0);
   int live = 0;
   for (int t = 0; t < r; ++t) {

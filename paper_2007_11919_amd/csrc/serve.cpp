@@ -384,9 +384,11 @@ mds_status mds_serve_add_model(mds_server* s, const mds_model* h, int32_t* model
   return MDS_OK;
 }
 
-mds_status mds_serve_submit(mds_server* s, int32_t model_id, const void* X, int64_t n_pts, int64_t ldx,
-                            int32_t prec, void* Y, int64_t ldy, int64_t* ticket) {
+mds_status mds_serve_submit(mds_server* s, int32_t model_id, const void* X, int32_t dt, int64_t n_pts,
+                            int64_t ldx, int32_t prec, void* Y, int64_t ldy, int64_t* ticket) {
   if (!s || !ticket) return set_error(MDS_ERR_INVALID_ARG, "NULL argument");
+  // the serving kernels read X and write Y as float
+  if (dt != MDS_F32) return set_error(MDS_ERR_INVALID_ARG, "serving takes float32 rows (MDS_F32)");
   int mode;
   switch (prec) {
     case MDS_PREC_FP32: mode = MODE_F32; break;

@@ -3,13 +3,15 @@
 import ctypes
 
 from . import _lib
-from .api import PREC, _check, _check_matrix
+from .api import F32, PREC, _check, _check_matrix
 
 
 class Server:
     """Resident models + admission by bytes/slots + persistent graph steps."""
 
     def __init__(self, budget_bytes, max_slots=64, tiles_per_step=0):
+        import torch
+        self._device = torch.cuda.current_device()
         h = ctypes.c_void_p()
         _check(_lib.lib().mds_serve_create(int(budget_bytes), int(max_slots), int(tiles_per_step),
                                            ctypes.byref(h)))
@@ -23,16 +25,29 @@ class Server:
         return mid.value
 
     def submit(self, model_id, X, prec, Y):
-        """Queue rows X (device, float32) for model_id; results go to Y."""
+        """Queue rows X (device, float32, n x p) for model_id; results go to
+        Y (device, float32, n x >= r), both on the server's device."""
+        import torch
         _check_matrix(X, "X")
         _check_matrix(Y, "Y")
+        model = self._keep.get(int(model_id))
+        if model is None:
+            raise ValueError(f"unknown model id {model_id}")
+        if X.dtype != torch.float32 or Y.dtype != torch.float32:
+            raise ValueError("serving takes float32 X and Y")
         n = X.shape[0]
+        if X.shape[1] != model.p:
+            raise ValueError(f"X has {X.shape[1]} columns, the model has p = {model.p}")
+        if Y.shape[0] != n or Y.shape[1] < model.r:
+            raise ValueError(f"Y must be {n} x (>= {model.r})")
+        if X.device != Y.device or X.device.index != self._device:
+            raise ValueError("X and Y must sit on the server's device")
         ldx = X.stride(0) if n > 1 else X.shape[1]
         ldy = Y.stride(0) if n > 1 else Y.shape[1]
         t = _lib.c_i64()
-        _check(_lib.lib().mds_serve_submit(self._h, int(model_id), ctypes.c_void_p(X.data_ptr()), n,
-                                           ldx, PREC[prec], ctypes.c_void_p(Y.data_ptr()), ldy,
-                                           ctypes.byref(t)))
+        _check(_lib.lib().mds_serve_submit(self._h, int(model_id), ctypes.c_void_p(X.data_ptr()),
+                                           F32, n, ldx, PREC[prec], ctypes.c_void_p(Y.data_ptr()),
+                                           ldy, ctypes.byref(t)))
         return t.value
 
     def poll(self, ticket):

@@ -103,7 +103,7 @@ def test_serve_argument_errors_need_no_gpu(L):
     assert L.mds_serve_create(1 << 30, 0, 0, ctypes.byref(srv)) == 1
     assert L.mds_serve_create(1 << 30, 4, -1, ctypes.byref(srv)) == 1
     t = ctypes.c_int64()
-    assert L.mds_serve_submit(None, 0, None, 0, 1, 1, None, 1, ctypes.byref(t)) == 1
+    assert L.mds_serve_submit(None, 0, None, 0, 0, 1, 1, None, 1, ctypes.byref(t)) == 1
     L.mds_serve_destroy(None)  # no-op
 
 

@@ -137,6 +137,34 @@ def test_pivot_full_size_sampled_rows():
     assert e["maxabs_rms"] <= 1e-8, e
 
 
+@pytest.mark.parametrize("ratio,live", [(1e-3, False), (10 ** -2.75, False),
+                                        (10 ** -2.125, True), (1e-1, True)])
+def test_pivot_live_threshold(ratio, live):
+    """Liveness on the eigenvalues of C'C (sigma_k^2 > TAU sigma_1^2), as in
+    the oracle: points in R^2 with every point a pivot, so C = Q has
+    singular values 1 and ratio^2.  The dead cases have sigma_2 / sigma_1
+    between TAU and sqrt(TAU).  A direction this close to the threshold is
+    only resolved to about eps sigma_1^2 / sigma_2^2 through C'C, so live
+    columns are compared to 1e-6."""
+    rng = np.random.default_rng(9)
+    Z = rng.standard_normal((20, 2))
+    Z -= Z.mean(axis=0)
+    H, _ = np.linalg.qr(Z)
+    X = H * np.array([1.0, ratio]) + np.array([3.0, -2.0])
+    idx = np.arange(20)
+    Y, lam, r_eff = mds().pivot_mds(dev(X), 20, 2, idx=idx)
+    Yo, lamo, _ = opv.pivot_mds(X, idx, 2)
+    Y = Y.cpu().numpy()
+    assert r_eff == (2 if live else 1)
+    assert abs(lam[0] - lamo[0]) <= 1e-12
+    if live:
+        assert abs(lam[1] / lamo[1] - 1.0) <= 1e-6, (lam, lamo)
+        e = errors.column_errors(Y, Yo)
+        assert e["maxabs_rms"] <= 1e-6, e
+    else:
+        assert lam[1] == 0.0 and np.all(Y[:, 1] == 0.0)
+
+
 def test_pivot_error_codes():
     m = mds()
     X = dev(gen.small_gaussian(300, seed=13))

@@ -28,8 +28,7 @@ def dev(a):
 def check(Y, Yo, prec):
     e = errors.column_errors(Y, Yo)
     assert e["rms_rel"] <= TOL[prec], (prec, e)
-    if prec == "fp64":
-        assert e["maxabs_rms"] <= TOL[prec], e
+    assert e["maxabs_rms"] <= TOL[prec], (prec, e)
 
 
 def test_euclidean_distances_match_vector_path():

@@ -167,6 +167,43 @@ def test_planted_mistake_in_scale(monkeypatch):
         test_paper_design_statistics()
 
 
+def _two_scale_points(ratio, n=20, seed=9):
+    """n points in R^2 whose centred coordinates are orthogonal columns of
+    norms 1 and ratio (so with every point as a pivot C = Q has singular
+    values 1 and ratio^2), shifted away from the origin."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((n, 2))
+    Z -= Z.mean(axis=0)
+    H, _ = np.linalg.qr(Z)
+    return H * np.array([1.0, ratio]) + np.array([3.0, -2.0]), H
+
+
+@pytest.mark.parametrize("ratio,live", [
+    (1e-3, False),    # sigma_2 / sigma_1 = 1e-6: between TAU and sqrt(TAU)
+    (10 ** -2.75, False),  # sigma ratio 10^-5.5, eigenvalue ratio of C'C 1e-11
+    (10 ** -2.125, True),  # sigma ratio 10^-4.25, eigenvalue ratio 10^-8.5
+    (1e-1, True),
+])
+def test_live_threshold_on_eigenvalues_of_ctc(ratio, live):
+    """The eigenvalue test of Section 2 applied to C'C: sigma_k^2 > TAU
+    sigma_1^2.  The two dead cases have sigma_2 / sigma_1 above TAU, so a
+    test on sigma (or on lambda = sigma sqrt(n / l)) would keep them."""
+    X, H = _two_scale_points(ratio)
+    n = X.shape[0]
+    for Y, lam in [opv.pivot_mds(X, np.arange(n), 2)[:2],
+                   opv.pivot_mds_large(X, np.arange(n), 2, chunk=7)[:2]]:
+        # all points as pivots: lambda are the eigenvalues of Q, 1 and ratio^2
+        assert abs(lam[0] - 1.0) < 1e-12
+        if live:
+            # the chunked route takes sigma from the eigenvalues of C'C, good
+            # to about eps sigma_1^2 / (2 sigma_2^2) relative
+            assert abs(lam[1] / ratio ** 2 - 1.0) < 1e-6
+            sgn = np.sign(np.dot(Y[:, 1], H[:, 1]))
+            assert pins._rel(sgn * Y[:, 1], ratio * H[:, 1]) < 1e-6
+        else:
+            assert lam[1] == 0.0 and np.all(Y[:, 1] == 0.0)
+
+
 def test_large_route_matches_direct():
     X = gen.small_gaussian(3000, seed=21)[:, :6]
     idx = np.array(oracle.sample_landmarks(3000, 60, 2))
