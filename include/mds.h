@@ -159,6 +159,26 @@ mds_status mds_embed_from_sqdist(const mds_model* m, const void* A2, int32_t dt,
 mds_status mds_maxmin_landmarks(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx,
                                 int64_t l, int64_t first, int64_t* idx_out, void* stream);
 
+/* ---- MaxMin without allocation ---------------------------------------------
+ * For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * selection as mds_maxmin_landmarks, with the same arguments and the same
+ * result, computed with the row-major steps only, on a static device array
+ * of MDS_NOALLOC_SCRATCH_BYTES bytes that the library holds on each GPU it
+ * runs on until the process ends (its address is looked up once per
+ * device, on the first call there).  Calls no allocating routine.  Every
+ * call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams or threads) race,
+ * and the caller must serialise them.  Synchronous, like
+ * mds_maxmin_landmarks.
+ * Errors: as mds_maxmin_landmarks, plus INVALID_ARG when
+ * n > MDS_NOALLOC_MAX_N or l > MDS_NOALLOC_MAX_L (no work is done). */
+#define MDS_NOALLOC_MAX_N 1048576
+#define MDS_NOALLOC_MAX_L 16384
+#define MDS_NOALLOC_SCRATCH_BYTES 8585472
+mds_status mds_maxmin_landmarks_noalloc(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx,
+                                        int64_t l, int64_t first, int64_t* idx_out, void* stream);
+
 /* ---- pivot MDS (Section 3.1) ---------------------------------------------
  * With l pivot rows, C is the double-centred n x l block of squared
  * distances between all rows and the pivots, and its singular value

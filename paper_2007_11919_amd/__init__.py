@@ -6,8 +6,9 @@ is missing every call raises.
 """
 
 from .api import (F32, F64, PREC, MDSError, Model, divide_conquer, embed, embed_affine, embed_from_sqdist,
-                  fit_from_sqdist, fit_landmarks, free, maxmin_landmarks, pivot_mds, sample_landmarks)
+                  fit_from_sqdist, fit_landmarks, free, maxmin_landmarks, maxmin_landmarks_noalloc,
+                  pivot_mds, sample_landmarks)
 
 __all__ = ["F32", "F64", "PREC", "MDSError", "Model", "divide_conquer", "embed", "embed_affine", "embed_from_sqdist",
-           "fit_from_sqdist", "fit_landmarks", "free", "maxmin_landmarks", "pivot_mds",
+           "fit_from_sqdist", "fit_landmarks", "free", "maxmin_landmarks", "maxmin_landmarks_noalloc", "pivot_mds",
            "sample_landmarks"]

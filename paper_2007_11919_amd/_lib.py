@@ -31,6 +31,7 @@ SIGNATURES = {
     "mds_fit_from_sqdist": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, ctypes.POINTER(c_vp)]),
     "mds_embed_from_sqdist": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp]),
     "mds_maxmin_landmarks": (c_i32, [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, P_i64, c_vp]),
+    "mds_maxmin_landmarks_noalloc": (c_i32, [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, P_i64, c_vp]),
     "mds_pivot_mds": (c_i32, [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i32, c_u64, P_i64, c_vp, c_i64,
                               P_dbl, P_i32, c_vp]),
     "mds_embed_affine": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp]),

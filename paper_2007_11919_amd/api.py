@@ -232,6 +232,20 @@ def maxmin_landmarks(X, l, first=0, stream=None):
     return out
 
 
+def maxmin_landmarks_noalloc(X, l, first=0, stream=None):
+    """mds_maxmin_landmarks_noalloc: as maxmin_landmarks, on the library's
+    static scratch array (no device allocation; n <= 2^20, l <= 16384;
+    calls on one GPU must not overlap)."""
+    _check_matrix(X, "X")
+    n, p = X.shape
+    out = np.empty(l, dtype=np.int64)
+    ldx = X.stride(0) if n > 1 else p
+    _check(_lib.lib().mds_maxmin_landmarks_noalloc(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n, p, ldx,
+                                                   l, first, out.ctypes.data_as(_lib.P_i64),
+                                                   _stream_ptr(stream)))
+    return out
+
+
 def pivot_mds(X, l, r, seed=0, idx=None, Y=None, stream=None):
     """mds_pivot_mds: pivot MDS of the rows of X; returns (Y, lam, r_eff)."""
     import torch

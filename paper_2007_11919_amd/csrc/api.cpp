@@ -277,6 +277,23 @@ mds_status mds_maxmin_landmarks(const void* X, int32_t dt, int64_t n, int64_t p,
   return s;
 }
 
+mds_status mds_maxmin_landmarks_noalloc(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx,
+                                        int64_t l, int64_t first, int64_t* idx_out, void* stream) {
+  if (!X || !idx_out) return set_error(MDS_ERR_INVALID_ARG, "X or idx_out is NULL");
+  if (dt != MDS_F32 && dt != MDS_F64) return set_error(MDS_ERR_INVALID_ARG, "dt must be MDS_F32 or MDS_F64");
+  if (p < 1 || ldx < p) return set_error(MDS_ERR_INVALID_ARG, "need p >= 1 and ldx >= p");
+  if (l < 1 || l > n) return set_error(MDS_ERR_INVALID_ARG, "need 1 <= l <= n");
+  if (first < 0 || first >= n) return set_error(MDS_ERR_INVALID_ARG, "first out of range");
+  if (n > MDS_NOALLOC_MAX_N)
+    return set_error(MDS_ERR_INVALID_ARG, "n exceeds MDS_NOALLOC_MAX_N (1048576) for the no-allocation MaxMin");
+  if (l > MDS_NOALLOC_MAX_L)
+    return set_error(MDS_ERR_INVALID_ARG, "l exceeds MDS_NOALLOC_MAX_L (16384) for the no-allocation MaxMin");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  mds_status s = maxmin_on_device_noalloc(X, dt, n, p, ldx, l, first, idx_out, st);
+  if (s != MDS_OK) (void)hipStreamSynchronize(st);
+  return s;
+}
+
 mds_status mds_pivot_mds(const void* X, int32_t dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int32_t r,
                          uint64_t seed, const int64_t* idx_or_null, double* Y, int64_t ldy, double* lam,
                          int32_t* r_eff, void* stream) {

@@ -154,6 +154,10 @@ mds_status dense_top_eigen(double* G, int d, int r, double* lam, double* U, int*
 // MaxMin landmarks and pivot MDS (pivot.hip); arguments validated by the API
 mds_status maxmin_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
                             int64_t first, int64_t* idx_host, hipStream_t st);
+// the same on the library's static scratch array (no allocation); sizes
+// checked by the API against MDS_NOALLOC_MAX_N / _L
+mds_status maxmin_on_device_noalloc(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
+                                    int64_t first, int64_t* idx_host, hipStream_t st);
 mds_status pivot_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int r,
                            const int64_t* idx_host, double* Y, int64_t ldy, double* lam_host,
                            int32_t* r_eff, hipStream_t st);

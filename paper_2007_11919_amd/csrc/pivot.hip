@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mds_internal.h"
@@ -690,6 +691,48 @@ __global__ void k_affine_shift(const double* __restrict__ A, const double* __res
   b[t] = -acc;
 }
 
+// idx[0] = first and flag = 0 (a fill kernel rather than a memset and a
+// host copy, so the steps need no host data once launched)
+__global__ void k_mm_init(int64_t* __restrict__ idx, int64_t first, int* __restrict__ flag) {
+  if (threadIdx.x == 0) {
+    idx[0] = first;
+    flag[0] = 0;
+  }
+}
+
+// The steps of MaxMin on buffers the caller provides: dmin (n), bval and
+// bidx (one per row block), idx (l), flag (1); Xt (p x ldt) when the
+// column-major copy is used, else NULL.  Copies idx to the host and waits.
+template <typename TX>
+mds_status maxmin_steps(const TX* X, int64_t ldx, int64_t n, int64_t p, int64_t l, int64_t first,
+                        int64_t* idx_host, hipStream_t st, double* dmin, double* bval, int64_t* bidx,
+                        int64_t* idx, int* flag, TX* Xt, int64_t ldt) {
+  const int nb = (int)((n + MM_ROWS - 1) / MM_ROWS);
+  k_mm_init<<<1, 64, 0, st>>>(idx, first, flag);
+  PV_LAUNCH("maxmin init");
+  if (Xt) {
+    k_mm_transpose<TX><<<dim3((unsigned)(ldt / 32), (unsigned)((p + 31) / 32)), 256, 0, st>>>(X, ldx, n, p,
+                                                                                               Xt, ldt);
+    PV_LAUNCH("maxmin column-major copy");
+  }
+  constexpr int64_t ROWS_T = 256 * (16 / (int64_t)sizeof(TX));
+  const int nbs = Xt ? (int)(ldt / ROWS_T) : nb;
+  for (int s = 0; s + 1 < l; ++s) {
+    if (Xt)
+      k_mm_step_t<TX><<<nbs, 256, 0, st>>>(Xt, ldt, n, p, X, ldx, idx, s, dmin, bval, bidx);
+    else
+      k_mm_step<TX><<<nbs, 256, 0, st>>>(X, ldx, n, p, idx, s, dmin, bval, bidx);
+    k_mm_pick<<<1, 256, 0, st>>>(bval, bidx, nbs, idx, s + 1, flag);
+  }
+  PV_LAUNCH("maxmin steps");
+  int hflag = 0;
+  PV_HIP(hipMemcpyAsync(idx_host, idx, sizeof(int64_t) * l, hipMemcpyDeviceToHost, st));
+  PV_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  PV_HIP(hipStreamSynchronize(st));
+  if (hflag) return set_error(MDS_ERR_DEGENERATE, "fewer than l distinct points");
+  return MDS_OK;
+}
+
 template <typename TX>
 mds_status maxmin_run(const TX* X, int64_t ldx, int64_t n, int64_t p, int64_t l, int64_t first,
                       int64_t* idx_host, hipStream_t st) {
@@ -704,38 +747,66 @@ mds_status maxmin_run(const TX* X, int64_t ldx, int64_t n, int64_t p, int64_t l,
   PV_HIP(alloc(bidx, sizeof(int64_t) * nb));
   PV_HIP(alloc(idx, sizeof(int64_t) * l));
   PV_HIP(alloc(flag, sizeof(int)));
-  PV_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
-  PV_HIP(hipMemcpyAsync(idx.p, &first, sizeof(int64_t), hipMemcpyHostToDevice, st));
   // column-major copy when there is room for it (else the row-major steps)
   constexpr int64_t ROWS_T = 256 * (16 / (int64_t)sizeof(TX));
   const int64_t ldt = (n + ROWS_T - 1) / ROWS_T * ROWS_T;
-  const int nbt = (int)(ldt / ROWS_T);  // <= nb
   Buf Xt;
   bool col_major = l > 1 && p <= MM_MAXP && alloc(Xt, sizeof(TX) * p * ldt) == hipSuccess;
   if (!col_major) (void)hipGetLastError();
-  if (col_major) {
-    k_mm_transpose<TX><<<dim3((unsigned)(ldt / 32), (unsigned)((p + 31) / 32)), 256, 0, st>>>(
-        X, ldx, n, p, Xt.get<TX>(), ldt);
-    PV_LAUNCH("maxmin column-major copy");
+  return maxmin_steps<TX>(X, ldx, n, p, l, first, idx_host, st, dmin.get<double>(), bval.get<double>(),
+                          bidx.get<int64_t>(), idx.get<int64_t>(), flag.get<int>(),
+                          col_major ? Xt.get<TX>() : nullptr, ldt);
+}
+
+// ---- MaxMin without allocation ----
+// One static device array per GPU holds the step buffers, laid out for the
+// largest accepted call (MDS_NOALLOC_MAX_N rows, MDS_NOALLOC_MAX_L
+// landmarks); every call on a GPU reuses that GPU's copy, so calls that
+// overlap on one GPU race.  Only the row-major steps run (the column-major
+// copy of X would not fit a bounded array).
+constexpr int64_t NA_NB = (MDS_NOALLOC_MAX_N + MM_ROWS - 1) / MM_ROWS;
+constexpr size_t na_round(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t NA_OFF_BVAL = na_round(sizeof(double) * MDS_NOALLOC_MAX_N);
+constexpr size_t NA_OFF_BIDX = NA_OFF_BVAL + na_round(sizeof(double) * NA_NB);
+constexpr size_t NA_OFF_IDX = NA_OFF_BIDX + na_round(sizeof(int64_t) * NA_NB);
+constexpr size_t NA_OFF_FLAG = NA_OFF_IDX + na_round(sizeof(int64_t) * MDS_NOALLOC_MAX_L);
+constexpr size_t NA_BYTES = NA_OFF_FLAG + 256;
+static_assert(NA_BYTES == MDS_NOALLOC_SCRATCH_BYTES, "scratch size stated in the header");
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+// device address of this GPU's scratch array, looked up once per device
+// (the name `scratch` is a host-side stand-in and must not reach a kernel)
+constexpr int NA_MAX_DEV = 64;
+std::mutex na_mu;
+void* na_ptr[NA_MAX_DEV] = {};
+
+mds_status scratch_for_current_device(unsigned char** out) {
+  int dev = 0;
+  PV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NA_MAX_DEV) return set_error(MDS_ERR_INVALID_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> g(na_mu);
+  if (!na_ptr[dev]) {
+    void* ptr = nullptr;
+    PV_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return set_error(MDS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    na_ptr[dev] = ptr;
   }
-  const int nbs = col_major ? nbt : nb;
-  for (int s = 0; s + 1 < l; ++s) {
-    if (col_major)
-      k_mm_step_t<TX><<<nbs, 256, 0, st>>>(Xt.get<TX>(), ldt, n, p, X, ldx, idx.get<int64_t>(), s,
-                                           dmin.get<double>(), bval.get<double>(), bidx.get<int64_t>());
-    else
-      k_mm_step<TX><<<nbs, 256, 0, st>>>(X, ldx, n, p, idx.get<int64_t>(), s, dmin.get<double>(),
-                                         bval.get<double>(), bidx.get<int64_t>());
-    k_mm_pick<<<1, 256, 0, st>>>(bval.get<double>(), bidx.get<int64_t>(), nbs, idx.get<int64_t>(), s + 1,
-                                 flag.get<int>());
-  }
-  PV_LAUNCH("maxmin steps");
-  int hflag = 0;
-  PV_HIP(hipMemcpyAsync(idx_host, idx.p, sizeof(int64_t) * l, hipMemcpyDeviceToHost, st));
-  PV_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  PV_HIP(hipStreamSynchronize(st));
-  if (hflag) return set_error(MDS_ERR_DEGENERATE, "fewer than l distinct points");
+  *out = static_cast<unsigned char*>(na_ptr[dev]);
   return MDS_OK;
+}
+
+template <typename TX>
+mds_status maxmin_run_noalloc(const TX* X, int64_t ldx, int64_t n, int64_t p, int64_t l, int64_t first,
+                              int64_t* idx_host, hipStream_t st) {
+  unsigned char* base = nullptr;
+  mds_status s = scratch_for_current_device(&base);
+  if (s != MDS_OK) return s;
+  return maxmin_steps<TX>(X, ldx, n, p, l, first, idx_host, st, reinterpret_cast<double*>(base),
+                          reinterpret_cast<double*>(base + NA_OFF_BVAL),
+                          reinterpret_cast<int64_t*>(base + NA_OFF_BIDX),
+                          reinterpret_cast<int64_t*>(base + NA_OFF_IDX), reinterpret_cast<int*>(base + NA_OFF_FLAG),
+                          nullptr, 0);
 }
 
 template <typename TX>
@@ -900,6 +971,17 @@ mds_status maxmin_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t
   if (dt == MDS_F32)
     return maxmin_run<float>(static_cast<const float*>(X), ldx, n, p, l, first, idx_host, st);
   return maxmin_run<double>(static_cast<const double*>(X), ldx, n, p, l, first, idx_host, st);
+}
+
+mds_status maxmin_on_device_noalloc(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l,
+                                    int64_t first, int64_t* idx_host, hipStream_t st) {
+  if (l == 1) {
+    idx_host[0] = first;
+    return MDS_OK;
+  }
+  if (dt == MDS_F32)
+    return maxmin_run_noalloc<float>(static_cast<const float*>(X), ldx, n, p, l, first, idx_host, st);
+  return maxmin_run_noalloc<double>(static_cast<const double*>(X), ldx, n, p, l, first, idx_host, st);
 }
 
 mds_status pivot_on_device(const void* X, int dt, int64_t n, int64_t p, int64_t ldx, int64_t l, int r,

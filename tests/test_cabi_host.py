@@ -134,3 +134,15 @@ def test_next_row_entry_points_reject_bad_arguments_without_gpu(L):
     assert L.mds_fit_from_sqdist(fake, 10, 9, 2, None, ctypes.byref(model)) == 1
     assert L.mds_embed_from_sqdist(None, fake, 0, 10, 10, 1, fake, 2, None) == 1
     assert L.mds_embed_affine(None, fake, 0, 10, 4, 1, fake, 2, None) == 1
+
+
+def test_noalloc_maxmin_limits_need_no_gpu(L):
+    """The no-allocation MaxMin rejects sizes past its static array before
+    any device work, with a message that names the limit."""
+    out = (ctypes.c_int64 * 4)()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the size checks come first
+    assert L.mds_maxmin_landmarks_noalloc(fake, 0, (1 << 20) + 1, 3, 3, 2, 0, out, None) == 1
+    assert b"MDS_NOALLOC_MAX_N" in L.mds_last_error()
+    assert L.mds_maxmin_landmarks_noalloc(fake, 0, 1 << 20, 3, 3, 16385, 0, out, None) == 1
+    assert b"MDS_NOALLOC_MAX_L" in L.mds_last_error()
+    assert L.mds_maxmin_landmarks_noalloc(None, 0, 10, 3, 3, 2, 0, out, None) == 1
