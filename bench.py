@@ -5,28 +5,39 @@ and the FP64 fit (gather, squared distances, double centring, Lanczos
 eigenpairs, finalisation) followed by the fused FP32 embed of every row.
 `value` is rows per second over the timed steps, inputs resident in HBM.
 
-Default workload: 1,000,000 x 100 Gaussian rows (first 10 std devs 20 -> 2,
-then 1), l = 1000 landmarks, r = 10.  Also reported on the same data:
-the split-BF16 embed (speed-up and error), the embed kernel's roofline
-fraction, serving latency (p50/p99) at three loads, and the FP64 oracle on
-the host cores (bounded sample).  Further legs, each with its own roofline
-and error check: the embed from squared dissimilarities (Section 2 input),
-the affine form of eq. (2), MaxMin landmark selection and pivot MDS
-(Section 3.1), and divide-and-conquer MDS (Section 3.2) on the simulation
-design of Section 4.1.
+Headline workload: 1,000,000 x 784 integer rows 0..255 from a 10-component
+Gaussian mixture (std 40; image-like data standing in for the grey-scale
+image set of Section 5), l = 2000 landmarks, r = 10.  On the same data: the
+split-BF16 and split-FP16 embeds (speed-up and error; which products ran),
+the FP64 embed, the embed kernel's roofline fraction, and the FP64 oracle
+on the host cores (bounded sample).
 
-    python bench.py [--steps K] [--warmup W] [--workload wide|image]
-    python bench.py --only-embed fp32 --iters 20     (for rocprofv3 runs)
-    python bench.py --only-fit --iters 5              (for rocprofv3 runs)
+Further legs, each with its own error check:
+* 1,000,000 x 100 Gaussian rows (std 20 -> 2 on 10 columns, 1 on 90),
+  l = 1000, r = 10: the same step and embed figures, serving (20,000
+  requests of 1..200,000 rows at three loads, FP32 and split BF16), the
+  embed from squared dissimilarities (Section 2 input), the affine form of
+  eq. (2), MaxMin landmark selection and pivot MDS (Section 3.1), and
+  divide-and-conquer MDS (Section 3.2) on the simulation design of
+  Section 4.1;
+* 5,000 x 10 FP64 rows (std 15, 10, 1, ...), l = 200, r = 2: latency of the
+  fit and the embed, beside the oracle;
+* 48 fitted models served together under a 24 GiB budget (p in {10, 50,
+  100, 784} x r in {2, 5, 10, 20} x 3, l log-uniform in [500, 4000]),
+  FP32 and split BF16, with the error against the oracle per (p, r).
+
+    python bench.py [--steps K] [--warmup W] [--workload image|wide]
+    python bench.py --only-embed fp32 --workload image --iters 20   (rocprofv3 runs)
+    python bench.py --only-fit --iters 5                             (rocprofv3 runs)
     python bench.py --only-dc | --only-affine | --only-sqdist | --only-pivot --iters K
-                                                      (the other kernels, for rocprofv3 runs)
-    python bench.py --copy-calib 1073741824           (counter calibration)
+    python bench.py --copy-calib 1073741824                          (counter calibration)
 """
 
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -36,6 +47,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
+PEAK_FP64_MFMA = 78.6e12    # MI355X dense FP64 matrix, FLOP/s
 PEAK_BF16_MFMA = 2.5e15     # MI355X dense BF16 matrix, FLOP/s
 PEAK_HBM = 8.0e12           # bytes/s
 
@@ -48,18 +60,22 @@ WORKLOADS = {
                        "10-component Gaussian mixture (std 40), l=2000 landmarks, r=10; "
                        "FP64 fit, FP32 embed"),
 }
+SMALL = dict(n=5000, p=10, l=200, r=2, seeds=(0, 1, 2),
+             desc="interpolation MDS, 5,000 x 10 FP64 Gaussian rows (std 15, 10, 1 x 8), "
+                  "l=200 landmarks, r=2; FP64 fit and embed")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_data(name):
+def make_data(name, n=None):
     from synth import generators as gen
     w = WORKLOADS[name]
+    n = w["n"] if n is None else n
     if name == "wide":
-        return gen.wide_gaussian(w["n"], seed=12)
-    return gen.image_mixture(w["n"], p=w["p"], seed=13)
+        return gen.wide_gaussian(n, seed=12)
+    return gen.image_mixture(n, p=w["p"], seed=13)
 
 
 def flops_per_point(p, l, r):
@@ -114,8 +130,47 @@ def counters_for(kernel_tag):
         return None
 
 
-def serving_run(mds, torch, model, Xd, prec, count, seed, budget):
-    """Poisson load at three fractions of the measured saturated capacity."""
+def host_info():
+    """CPU model, usable cores and the BLAS the oracle runs on."""
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = []
+    try:
+        from threadpoolctl import threadpool_info
+        for i in threadpool_info():
+            if i.get("user_api") == "blas":
+                blas.append(f"{i.get('internal_api')} {i.get('version')} ({i.get('num_threads')} threads)")
+    except Exception:  # threadpoolctl absent: report what numpy was built with
+        blas.append("unknown")
+    return {"cpu_model": model, "cores": len(os.sched_getaffinity(0)), "blas": "; ".join(blas)}
+
+
+def one_thread():
+    """Context that limits the BLAS to one thread (for a per-core rate)."""
+    from threadpoolctl import threadpool_limits
+    return threadpool_limits(limits=1, user_api="blas")
+
+
+def max_row_error(Y, R, scale):
+    """Worst RMS and worst max over columns of |Y - R| / scale_k (device
+    tensors; scale: column RMS of the reference over the whole pool)."""
+    d = (Y.double() - R.double()).abs() / scale
+    return float(d.pow(2).mean(0).sqrt().max()), float(d.max())
+
+
+def serving_run(mds, torch, model, Xd, prec, count, seed, budget, Y64, fit_o, X):
+    """Poisson load at three fractions of the measured saturated capacity.
+    Requests are slices of the pool at random offsets.  Every served result
+    is compared with the oracle-validated GPU FP64 embed of the same pool
+    rows (Y64), and every 10th request's first rows (up to 256) with the
+    host oracle itself (fit_o, X)."""
+    import oracle
     from paper_2007_11919_amd.serve import Server
     from synth import generators as gen
     n = Xd.shape[0]
@@ -152,7 +207,7 @@ def serving_run(mds, torch, model, Xd, prec, count, seed, budget):
     run(None)  # warm-up
     makespan, _ = run(None)
     cap_rps = count / makespan
-    out = {"precision": prec, "requests": count, "mean_points": float(sizes.mean()),
+    out = {"precision": prec, "requests": count, "points": total, "mean_points": float(sizes.mean()),
            "saturated_points_per_s": float(total / makespan),
            "saturated_requests_per_s": float(cap_rps), "loads": []}
     for rho in (0.5, 0.8, 0.95):
@@ -164,19 +219,44 @@ def serving_run(mds, torch, model, Xd, prec, count, seed, budget):
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "points_per_s": float(total / span)})
     srv.close()
+    # results of the last run against the references
+    scale = Y64.double().pow(2).mean(0).sqrt()
+    worst_rms, worst_max = 0.0, 0.0
+    for i in range(count):
+        s, o, y0 = int(sizes[i]), int(offs[i]), int(ystart[i])
+        a, b = max_row_error(Yall[y0:y0 + s], Y64[o:o + s], scale)
+        worst_rms, worst_max = max(worst_rms, a), max(worst_max, b)
+    sc = scale.cpu().numpy()
+    o_rms, o_max, o_rows = 0.0, 0.0, 0
+    for i in range(0, count, 10):
+        s, o, y0 = min(int(sizes[i]), 256), int(offs[i]), int(ystart[i])
+        Yo = oracle.interpolate(fit_o, X[o:o + s].astype(np.float64))
+        d = np.abs(Yall[y0:y0 + s].cpu().numpy().astype(np.float64) - Yo) / sc
+        o_rms = max(o_rms, float(np.sqrt((d * d).mean(0)).max()))
+        o_max = max(o_max, float(d.max()))
+        o_rows += s
+    out["error"] = {
+        "every_request_vs_gpu_fp64": {"rms": worst_rms, "max": worst_max},
+        "every_10th_request_vs_oracle": {"rms": o_rms, "max": o_max, "rows": o_rows},
+        "reading": "per request, worst column of RMS and of max |served - reference| over the "
+                   "column RMS of the reference on the whole pool"}
+    del Yall
     return out
 
 
-def serving_multi(mds, torch, count, seed, budget, precs=("fp32", "split_bf16")):
+def serving_multi(mds, torch, count, seed, budget, pool_rows=500_000, precs=("fp32", "split_bf16")):
     """Multi-tenant serving: 48 fitted models (p in {10, 50, 100, 784} x r in
     {2, 5, 10, 20} x 3, l log-uniform in [500, 4000]) resident under a byte
     budget; a stream of requests (sizes log-uniform in [1, 500,000], model
     uniform) at 0.8 of the measured saturated rate.  A sample of results is
-    compared bit for bit with a plain mds_embed of the same rows."""
+    compared bit for bit with a plain mds_embed of the same rows, and for
+    each (p, r) the model with the fewest landmarks is refitted by the host
+    oracle, which checks up to 512 rows of that model's largest request."""
+    import oracle
     from paper_2007_11919_amd.serve import Server
+    from synth import errors
     from synth import generators as gen
     rng = np.random.Generator(np.random.PCG64(seed))
-    pool_rows = 500_000
     pools = {
         10: gen.gaussian_columns(pool_rows, gen.SIGMAS_SMALL, 21, dtype=np.float32),
         50: gen.gaussian_columns(pool_rows, gen.SIGMAS_P50, 22, dtype=np.float32),
@@ -184,21 +264,33 @@ def serving_multi(mds, torch, count, seed, budget, precs=("fp32", "split_bf16"))
         784: gen.image_mixture(pool_rows, seed=24),
     }
     dpools = {p: torch.from_numpy(x).cuda() for p, x in pools.items()}
-    del pools
-    models = []
+    models, specs = [], []
     t = time.perf_counter()
     for rep in range(3):
         for p in (10, 50, 100, 784):
             for r in (2, 5, 10, 20):
                 l = int(round(np.exp(rng.uniform(np.log(500), np.log(4000)))))
-                models.append((p, mds.fit_landmarks(dpools[p], l, r, seed=rep * 100 + p + r)))
+                fseed = rep * 100 + p + r
+                models.append((p, mds.fit_landmarks(dpools[p], l, r, seed=fseed)))
+                specs.append((p, r, l, fseed))
     torch.cuda.synchronize()
     fit_s = time.perf_counter() - t
-    out = {"models": len(models), "budget_bytes": budget, "fit_all_s": fit_s,
+    out = {"models": len(models), "budget_bytes": budget, "fit_all_s": fit_s, "pool_rows": pool_rows,
            "model_bytes": int(sum(m.nbytes for _, m in models)), "runs": []}
     sizes = gen.request_sizes(count, 500_000, seed + 1)
     which = rng.integers(0, len(models), size=count)
     offs = [int(rng.integers(0, pool_rows - s + 1)) for s in sizes]
+    # per (p, r): the model with the fewest landmarks, and its largest request
+    checks = {}
+    for mi, (p, r, l, _) in enumerate(specs):
+        if (p, r) not in checks or l < specs[checks[(p, r)]][2]:
+            checks[(p, r)] = mi
+    fits_o = {}
+    t = time.perf_counter()
+    for (p, r), mi in checks.items():
+        _, _, l, fseed = specs[mi]
+        fits_o[mi] = oracle.fit_landmarks(pools[p], l, r, seed=fseed)
+    oracle_fit_s = time.perf_counter() - t
     for prec in precs:
         srv = Server(budget_bytes=budget, max_slots=512, tiles_per_step=4096)
         ids = [srv.add_model(m) for _, m in models]
@@ -235,6 +327,19 @@ def serving_multi(mds, torch, count, seed, budget, precs=("fp32", "split_bf16"))
             s, o = int(sizes[i]), offs[i]
             ref = mds.embed(m, dpools[p][o:o + s], prec=prec)
             same &= bool(torch.equal(ref, ys[i]))
+        # oracle check per (p, r)
+        per_class = []
+        for (p, r), mi in sorted(checks.items()):
+            reqs = np.flatnonzero(which == mi)
+            if len(reqs) == 0:
+                continue
+            i = int(reqs[np.argmax(sizes[reqs])])
+            s, o = min(int(sizes[i]), 512), offs[i]
+            Yo = oracle.interpolate(fits_o[mi], pools[p][o:o + s].astype(np.float64))
+            e = errors.column_errors(ys[i][:s].cpu().numpy(), Yo)
+            per_class.append({"p": p, "r": r, "l": specs[mi][2], "rows": s,
+                              "r_eff": int(models[mi][1].r_eff),
+                              "rms_rel": e["rms_rel"], "maxabs_rms": e["maxabs_rms"]})
         st = srv.stats()
         srv.close()
         out["runs"].append({
@@ -244,8 +349,10 @@ def serving_multi(mds, torch, count, seed, budget, precs=("fp32", "split_bf16"))
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "points_per_s_at_load": float(sizes.sum() / span),
-            "steps": int(st["steps"]), "bitwise_equal_to_plain_embed": same})
+            "steps": int(st["steps"]), "bitwise_equal_to_plain_embed": same,
+            "err_vs_oracle_per_class": per_class})
         del ys
+    out["oracle_fit_s"] = oracle_fit_s
     for _, m in models:
         m.free()
     return out
@@ -429,33 +536,220 @@ def dc_leg(mds, torch, iters, cpu):
     return out
 
 
-def cpu_baseline(name, X, w, sample_rows, Ys_gpu):
-    """The FP64 oracle, as it stands, on the host cores: full fit plus the
-    embed of a bounded sample of rows, scaled to rows per second of a whole
-    pass.  Also returns the GPU results' error on that sample."""
+def cpu_baseline(name, X, w, sample_rows, one_thread_rows, Ys_gpu):
+    """The FP64 oracle, as it stands, on the host cores: the full fit (once)
+    plus the embed of a random sample of rows (median of 3), scaled to rows
+    per second of a whole pass; also the embed rate of one thread on a
+    smaller sample.  Returns the oracle fit, the sample rows and the GPU
+    results' error on them."""
     import oracle
     from synth import errors
-    threads = len(os.sched_getaffinity(0))
+    info = host_info()
     t = time.perf_counter()
     fit = oracle.fit_landmarks(X, w["l"], w["r"], seed=0)
     t_fit = time.perf_counter() - t
     rows = np.sort(np.random.Generator(np.random.PCG64(99)).choice(X.shape[0], sample_rows,
                                                                    replace=False))
-    t = time.perf_counter()
-    Yo = oracle.interpolate(fit, X[rows])
-    t_emb = time.perf_counter() - t
-    per_row = t_emb / sample_rows
+    Xs = X[rows]
+    t_emb = []
+    for _ in range(3):
+        t = time.perf_counter()
+        Yo = oracle.interpolate(fit, Xs)
+        t_emb.append(time.perf_counter() - t)
+    t_med = float(np.median(t_emb))
+    per_row = t_med / sample_rows
     whole = t_fit + per_row * X.shape[0]
+    with one_thread():
+        t = time.perf_counter()
+        oracle.interpolate(fit, Xs[:one_thread_rows])
+        t1 = time.perf_counter() - t
     errs = {}
     for prec, Y in Ys_gpu.items():
         e = errors.column_errors(Y[rows], Yo)
         errs[prec] = {k: e[k] for k in ("rms_rel", "maxabs_rms", "frob_rel")}
-    base = {"value": float(X.shape[0] / whole), "unit": "points/s", "cores": threads,
+    base = {"value": float(X.shape[0] / whole), "unit": "points/s", "cores": info["cores"],
             "kind": "oracle",
-            "sample": f"oracle fit on all {w['l']} landmarks ({t_fit:.2f} s) + embed of "
-                      f"{sample_rows} random rows ({t_emb:.2f} s), scaled to {X.shape[0]} rows",
-            "fit_s": t_fit, "embed_s_per_row": per_row}
-    return base, errs
+            "sample": f"oracle fit on all {w['l']} landmarks, timed once ({t_fit:.2f} s) + embed of "
+                      f"{sample_rows} random rows (median of 3: {t_med:.2f} s), scaled to "
+                      f"{X.shape[0]} rows",
+            "cpu_model": info["cpu_model"], "blas": info["blas"],
+            "fit_s": t_fit, "embed_s_per_row": per_row, "embed_runs_s": t_emb,
+            "one_thread": {"rows": one_thread_rows, "s": t1,
+                           "embed_points_per_s": one_thread_rows / t1}}
+    return base, errs, fit, rows, Yo
+
+
+def lo_parts_zero(X):
+    """True when every value is an integer of magnitude <= 256, so that its
+    BF16 (and FP16) value is exact and both split lo parts are zero (the
+    landmark rows are rows of X)."""
+    return bool(np.all(np.abs(X) <= 256.0) and np.array_equal(X, np.rint(X)))
+
+
+def workload_run(mds, torch, name, args, dev, cpu):
+    """The step (sampler + fit + FP32 embed of every row) on one workload,
+    timed over args.steps after args.warmup, then the fit and each embed
+    precision alone, errors against the GPU FP64 embed (all rows) and the
+    host oracle (a sample).  Returns the report and what later legs reuse."""
+    from synth import errors
+    w = WORKLOADS[name]
+    log(f"[{name}] generating data")
+    X = make_data(name)
+    Xd = torch.from_numpy(X).to(dev)
+    torch.cuda.synchronize()
+    n = w["n"]
+
+    def step():
+        model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
+        Y = mds.embed(model, Xd, prec="fp32")
+        torch.cuda.synchronize()
+        model.free()
+        return Y
+
+    log(f"[{name}] warm-up")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[{name}] timed steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+
+    # fit alone (median of five) and the embed kernels alone, on one model
+    fit_times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
+        torch.cuda.synchronize()
+        fit_times.append((time.perf_counter() - t) * 1e3)
+        if len(fit_times) < 5:
+            model.free()
+    fit_stats = model.fit_stats()
+    log(f"[{name}] embeds")
+    t32, Y32 = time_embed(mds, torch, model, Xd, "fp32", args.embed_iters)
+    tbf, Ybf = time_embed(mds, torch, model, Xd, "split_bf16", args.embed_iters)
+    t16, Y16 = time_embed(mds, torch, model, Xd, "split_fp16", args.embed_iters)
+    t64, Y64 = time_embed(mds, torch, model, Xd, "fp64", max(3, args.embed_iters // 4))
+    Y64n = Y64.cpu().numpy()
+    err_vs64 = {}
+    for prec, Y in (("fp32", Y32), ("split_bf16", Ybf), ("split_fp16", Y16)):
+        e = errors.column_errors(Y.cpu().numpy(), Y64n)
+        err_vs64[prec] = {k: e[k] for k in ("rms_rel", "maxabs_rms", "frob_rel")}
+
+    fpp = flops_per_point(w["p"], w["l"], w["r"])
+    flops = fpp * n
+    lo_zero = lo_parts_zero(X)
+    roof = {"bound": "mfma", "achieved": flops / t32 / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+            "unit": "TFLOP/s", "frac": flops / t32 / PEAK_FP32_MFMA,
+            "traffic": counters_for(f"embed_fp32_{name}"),
+            "kernel": embed_kernel("fp32", w["p"], w["l"], w["r"]),
+            "flops_per_point": fpp, "points_per_launch": n}
+    rep = {
+        "ms_per_step": total / args.steps * 1e3, "points_per_s": n * args.steps / total,
+        "config": {"workload": w["desc"], "n": n, "p": w["p"], "l": w["l"], "r": w["r"]},
+        "roofline": roof,
+        "fit_ms": float(np.median(fit_times)), "fit_lanczos_steps": fit_stats["lanczos_steps"],
+        "embed_fp32_ms": t32 * 1e3, "embed_fp32_points_per_s": n / t32,
+        "split_bf16": {
+            "embed_ms": tbf * 1e3, "points_per_s": n / tbf, "speedup_vs_fp32": t32 / tbf,
+            "algorithmic_tflops": flops / tbf / 1e12,
+            "frac_of_bf16_peak_algorithmic": flops / tbf / PEAK_BF16_MFMA,
+            "kernel": embed_kernel("bf16", w["p"], w["l"], w["r"]),
+            "lo_passes_skipped": lo_zero,
+            "products": ("hi.hi only: data and landmarks are integers 0..255, exact in BF16, so "
+                         "every lo part is zero and the lo products are skipped"
+                         if lo_zero else
+                         "hi.hi + lo.hi + hi.lo + lo.lo (data lo parts nonzero)")},
+        "split_fp16": {"embed_ms": t16 * 1e3, "points_per_s": n / t16, "speedup_vs_fp32": t32 / t16},
+        "embed_fp64_ms": t64 * 1e3,
+        "err_vs_gpu_fp64_all_rows": err_vs64,
+    }
+    fit_o = None
+    if cpu:
+        log(f"[{name}] cpu baseline (oracle)")
+        base, errs, fit_o, _, _ = cpu_baseline(
+            name, X, w, args.cpu_sample if name == "wide" else args.cpu_sample // 10,
+            100_000 if name == "wide" else 20_000,
+            {"fp32": Y32.cpu().numpy(), "split_bf16": Ybf.cpu().numpy(),
+             "split_fp16": Y16.cpu().numpy(), "fp64": Y64n})
+        rep["cpu_baseline"] = base
+        rep["err_vs_oracle_sample"] = errs
+    return rep, dict(X=X, Xd=Xd, model=model, Y32=Y32, Y64=Y64, Y64n=Y64n, fit_o=fit_o)
+
+
+def small_leg(mds, torch, dev, cpu):
+    """Latency at 5,000 x 10, FP64 (fit and embed), each landmark seed: GPU
+    medians of 10 (wall time around a synchronous fit; HIP events around the
+    embed), the host oracle's medians of 10 (all cores, and one thread),
+    and the error against the oracle."""
+    import oracle
+    from synth import errors
+    from synth import generators as gen
+    s = SMALL
+    X = gen.small_gaussian(s["n"], seed=11)
+    Xd = torch.from_numpy(X).to(dev)
+    st = torch.cuda.current_stream()
+    out = {"config": s["desc"], "seeds": []}
+    for seed in s["seeds"]:
+        fits = []
+        for _ in range(11):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            model = mds.fit_landmarks(Xd, s["l"], s["r"], seed=seed)
+            fits.append((time.perf_counter() - t) * 1e3)
+            model.free()
+        model = mds.fit_landmarks(Xd, s["l"], s["r"], seed=seed)
+        Y = mds.embed(model, Xd, prec="fp64")
+        torch.cuda.synchronize()
+        embs, whole = [], []
+        for _ in range(10):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            mds.embed(model, Xd, prec="fp64", Y=Y)
+            e1.record(st)
+            torch.cuda.synchronize()
+            embs.append(e0.elapsed_time(e1))
+        for _ in range(10):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            m2 = mds.fit_landmarks(Xd, s["l"], s["r"], seed=seed)
+            mds.embed(m2, Xd, prec="fp64", Y=Y)
+            torch.cuda.synchronize()
+            whole.append((time.perf_counter() - t) * 1e3)
+            m2.free()
+        rec = {"landmark_seed": seed, "fit_ms_median": float(np.median(fits[1:])),
+               "embed_ms_median": float(np.median(embs)),
+               "fit_plus_embed_ms_median": float(np.median(whole)),
+               "points_per_s": s["n"] / (np.median(whole) / 1e3)}
+        fit_o = oracle.fit_landmarks(X, s["l"], s["r"], seed=seed)
+        Yo = oracle.interpolate(fit_o, X)
+        e = errors.column_errors(Y.cpu().numpy(), Yo)
+        rec["err_vs_oracle"] = {k: e[k] for k in ("rms_rel", "maxabs_rms")}
+        rec["landmarks_equal_oracle"] = bool(np.array_equal(model.landmarks(), fit_o.idx))
+        if cpu:
+            def oracle_once():
+                f = oracle.fit_landmarks(X, s["l"], s["r"], seed=seed)
+                oracle.interpolate(f, X)
+            tt = []
+            for _ in range(10):
+                t = time.perf_counter()
+                oracle_once()
+                tt.append((time.perf_counter() - t) * 1e3)
+            with one_thread():
+                t1 = []
+                for _ in range(10):
+                    t = time.perf_counter()
+                    oracle_once()
+                    t1.append((time.perf_counter() - t) * 1e3)
+            rec["oracle_ms_median"] = float(np.median(tt))
+            rec["oracle_one_thread_ms_median"] = float(np.median(t1))
+        model.free()
+        out["seeds"].append(rec)
+    return out
 
 
 def main():
@@ -463,14 +757,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="wide")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="image",
+                    help="headline workload (the other one runs as a leg unless --no-wide)")
     ap.add_argument("--embed-iters", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-sqdist", action="store_true")
-    ap.add_argument("--serve-multi", type=int, default=0,
-                    help="also run the 48-model multi-tenant serving mix with this many requests")
+    ap.add_argument("--serve-multi", type=int, default=20000,
+                    help="requests in the 48-model multi-tenant mix (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-wide", action="store_true", help="skip the legs on the other workload")
+    ap.add_argument("--no-small", action="store_true", help="skip the 5,000 x 10 FP64 latency leg")
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--only-embed", choices=["fp32", "split_bf16", "split_fp16", "fp64"])
     ap.add_argument("--iters", type=int, default=10)
@@ -519,21 +816,33 @@ def main():
         print(json.dumps({"only_dc": args.iters}))
         return
 
-    w = WORKLOADS[args.workload]
-    log(f"generating {args.workload} data")
-    X = make_data(args.workload)
-    Xd = torch.from_numpy(X).to(dev)
-    torch.cuda.synchronize()
-
-    if args.only_fit:
-        for _ in range(args.iters):
-            mds.fit_landmarks(Xd, w["l"], w["r"], seed=0).free()
+    if args.only_fit or args.only_affine or args.only_sqdist or args.only_pivot or args.only_embed:
+        w = WORKLOADS[args.workload]
+        log(f"generating {args.workload} data")
+        X = make_data(args.workload)
+        Xd = torch.from_numpy(X).to(dev)
         torch.cuda.synchronize()
-        print(json.dumps({"only_fit": args.iters}))
-        return
-
-    if args.only_affine or args.only_sqdist:
+        if args.only_fit:
+            for _ in range(args.iters):
+                mds.fit_landmarks(Xd, w["l"], w["r"], seed=0).free()
+            torch.cuda.synchronize()
+            print(json.dumps({"only_fit": args.iters}))
+            return
+        if args.only_pivot:
+            mds.maxmin_landmarks(Xd, 200, 0)
+            for _ in range(args.iters):
+                mds.pivot_mds(Xd, 200, 10, seed=4)
+            torch.cuda.synchronize()
+            print(json.dumps({"only": "pivot", "iters": args.iters}))
+            return
         model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
+        if args.only_embed:
+            Y = mds.embed(model, Xd, prec=args.only_embed)
+            for _ in range(args.iters):
+                mds.embed(model, Xd, prec=args.only_embed, Y=Y)
+            torch.cuda.synchronize()
+            print(json.dumps({"only_embed": args.only_embed, "iters": args.iters}))
+            return
         if args.only_affine:
             Y = mds.embed_affine(model, Xd, prec="fp32")
             for _ in range(args.iters):
@@ -554,125 +863,65 @@ def main():
         print(json.dumps({"only": "affine" if args.only_affine else "sqdist", "iters": args.iters}))
         return
 
-    if args.only_pivot:
-        mds.maxmin_landmarks(Xd, 200, 0)
-        for _ in range(args.iters):
-            mds.pivot_mds(Xd, 200, 10, seed=4)
-        torch.cuda.synchronize()
-        print(json.dumps({"only": "pivot", "iters": args.iters}))
-        return
-
-    if args.only_embed:
-        model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
-        Y = mds.embed(model, Xd, prec=args.only_embed)
-        for _ in range(args.iters):
-            mds.embed(model, Xd, prec=args.only_embed, Y=Y)
-        torch.cuda.synchronize()
-        print(json.dumps({"only_embed": args.only_embed, "iters": args.iters}))
-        return
-
-    n = w["n"]
-
-    def step():
-        model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
-        Y = mds.embed(model, Xd, prec="fp32")
-        torch.cuda.synchronize()
-        model.free()
-        return Y
-
-    log("warm-up")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("timed steps")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    ms_step = total / args.steps * 1e3
-    value = n * args.steps / total
-
-    # fit alone (median of five) and the embed kernels alone, on one model
-    fit_times = []
-    for _ in range(5):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
-        torch.cuda.synchronize()
-        fit_times.append((time.perf_counter() - t) * 1e3)
-        if len(fit_times) < 5:
-            model.free()
-    fit_ms = float(np.median(fit_times))
-    fit_stats = model.fit_stats()
-    t32, Y32 = time_embed(mds, torch, model, Xd, "fp32", args.embed_iters)
-    tbf, Ybf = time_embed(mds, torch, model, Xd, "split_bf16", args.embed_iters)
-    t16, Y16 = time_embed(mds, torch, model, Xd, "split_fp16", args.embed_iters)
-    t64, Y64 = time_embed(mds, torch, model, Xd, "fp64", max(3, args.embed_iters // 4))
-    Y64n = Y64.cpu().numpy()
-    from synth import errors
-    err_vs64 = {}
-    for prec, Y in (("fp32", Y32), ("split_bf16", Ybf), ("split_fp16", Y16)):
-        e = errors.column_errors(Y.cpu().numpy(), Y64n)
-        err_vs64[prec] = {k: e[k] for k in ("rms_rel", "maxabs_rms", "frob_rel")}
-
-    fpp = flops_per_point(w["p"], w["l"], w["r"])
-    flops = fpp * n
-    tag = f"embed_fp32_{args.workload}"
-    roof = {"bound": "mfma", "achieved": flops / t32 / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-            "unit": "TFLOP/s", "frac": flops / t32 / PEAK_FP32_MFMA,
-            "traffic": counters_for(tag), "kernel": embed_kernel("fp32", w["p"], w["l"], w["r"]),
-            "flops_per_point": fpp, "points_per_launch": n}
+    cpu = not args.no_cpu_baseline
+    head, h = workload_run(mds, torch, args.workload, args, dev, cpu)
+    w = WORKLOADS[args.workload]
     out = {
         "metric": "embedded points/s, FP32 vs split-BF16 at stated err; serving p50/p99 latency",
-        "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "value": head["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w["desc"], "n": n, "p": w["p"], "l": w["l"], "r": w["r"]},
-        "roofline": roof,
-        "fit_ms": fit_ms, "fit_lanczos_steps": fit_stats["lanczos_steps"],
-        "embed_fp32_ms": t32 * 1e3, "embed_fp32_points_per_s": n / t32,
-        "split_bf16": {"embed_ms": tbf * 1e3, "points_per_s": n / tbf, "speedup_vs_fp32": t32 / tbf,
-                       "algorithmic_tflops": flops / tbf / 1e12,
-                       "frac_of_bf16_peak_algorithmic": flops / tbf / PEAK_BF16_MFMA,
-                       "kernel": embed_kernel("bf16", w["p"], w["l"], w["r"])},
-        "split_fp16": {"embed_ms": t16 * 1e3, "points_per_s": n / t16, "speedup_vs_fp32": t32 / t16},
-        "embed_fp64_ms": t64 * 1e3,
-        "err_vs_gpu_fp64_all_rows": err_vs64,
-        "paper_context": "paper: 18.34 s for n=1e6, 100 columns, l=250, r=10 on one i9-10900K "
-                         "in R (about 54,500 points/s); different l, not a target",
     }
-    if args.workload == "wide" and not args.no_sqdist:
-        log("embedding from squared dissimilarities")
-        out["embed_from_sqdist"] = sqdist_leg(mds, torch, model, Xd, Y32, args.embed_iters)
-    if not args.no_affine:
-        log("affine form")
-        out["embed_affine"] = affine_leg(mds, torch, model, Xd, Y64n, args.embed_iters)
-    if args.workload == "wide" and not args.no_pivot:
-        log("maxmin and pivot MDS")
-        out["maxmin_pivot"] = pivot_leg(mds, torch, Xd, X, args.dc_iters, not args.no_cpu_baseline)
-    if args.workload == "wide" and not args.no_dc:
-        log("divide-and-conquer MDS")
-        out["divide_conquer"] = dc_leg(mds, torch, args.dc_iters, not args.no_cpu_baseline)
-    if not args.no_serve:
-        log("serving runs")
-        budget = 8 << 30
-        out["serving"] = {"budget_bytes": budget, "runs": [
-            serving_run(mds, torch, model, Xd, prec, args.serve_requests, 5, budget)
-            for prec in ("fp32", "split_bf16")]}
+    out.update({k: v for k, v in head.items() if k not in ("ms_per_step", "points_per_s")})
+    if not cpu:
+        out["cpu_baseline"] = None
+    out["paper_context"] = ("paper (R, one i9-10900K): interpolation MDS of 814,255 x 784 images "
+                            "with l=250 in 98.55 s (about 8,260 points/s), and of 10^6 x 100 rows "
+                            "with l=250 in 18.34 s (about 54,500 points/s); other l, not a target")
+    if args.workload == "image" and not args.no_affine:
+        log("[image] affine form")
+        out["embed_affine"] = affine_leg(mds, torch, h["model"], h["Xd"], h["Y64n"], args.embed_iters)
+    h["model"].free()
+    del h
+
+    if not args.no_wide and args.workload == "image":
+        torch.cuda.empty_cache()
+        wide, g = workload_run(mds, torch, "wide", args, dev, cpu)
+        model, Xd, X = g["model"], g["Xd"], g["X"]
+        if not args.no_sqdist:
+            log("[wide] embedding from squared dissimilarities")
+            wide["embed_from_sqdist"] = sqdist_leg(mds, torch, model, Xd, g["Y32"], args.embed_iters)
+        if not args.no_affine:
+            log("[wide] affine form")
+            wide["embed_affine"] = affine_leg(mds, torch, model, Xd, g["Y64n"], args.embed_iters)
+        if not args.no_pivot:
+            log("[wide] maxmin and pivot MDS")
+            wide["maxmin_pivot"] = pivot_leg(mds, torch, Xd, X, args.dc_iters, cpu)
+        if not args.no_serve:
+            log("[wide] serving runs")
+            fit_o = g["fit_o"]
+            if fit_o is None:
+                import oracle
+                fit_o = oracle.fit_landmarks(X, WORKLOADS["wide"]["l"], WORKLOADS["wide"]["r"], seed=0)
+            budget = 8 << 30
+            out["serving"] = {"model": WORKLOADS["wide"]["desc"], "budget_bytes": budget, "runs": [
+                serving_run(mds, torch, model, Xd, prec, args.serve_requests, 5, budget, g["Y64"],
+                            fit_o, X)
+                for prec in ("fp32", "split_bf16")]}
+        model.free()
+        del g, model, Xd, X
+        torch.cuda.empty_cache()
+        if not args.no_dc:
+            log("divide-and-conquer MDS")
+            wide["divide_conquer"] = dc_leg(mds, torch, args.dc_iters, cpu)
+        out["wide"] = wide
+    if not args.no_small:
+        log("5,000 x 10 FP64 latency")
+        out["small_fp64"] = small_leg(mds, torch, dev, cpu)
     if args.serve_multi:
         log("multi-tenant serving")
+        torch.cuda.empty_cache()
         out["serving_multi"] = serving_multi(mds, torch, args.serve_multi, 31, 24 << 30)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        base, errs = cpu_baseline(args.workload, X, w, args.cpu_sample,
-                                  {"fp32": Y32.cpu().numpy(), "split_bf16": Ybf.cpu().numpy(),
-                                   "split_fp16": Y16.cpu().numpy(), "fp64": Y64n})
-        out["cpu_baseline"] = base
-        out["err_vs_oracle_sample"] = errs
-    else:
-        out["cpu_baseline"] = None
-    model.free()
     print(json.dumps(out))
 
 
