@@ -1156,6 +1156,401 @@ __device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restr
   __syncthreads();
 }
 
+// ---- split precisions with 32 x 32 x 16 matrix-core products ----
+// A 512-thread block (two waves per SIMD) owns 128 data rows and walks the
+// landmarks 512 at a time; wave (h, q) holds the 64 x 128 block of S^T for
+// rows 64 h .. 64 h + 63 and landmarks 128 q .. 128 q + 127 of the pass
+// (8 accumulators of 32 x 32).  Per 32-value chunk of the contraction:
+//   * the landmark parts come from the chunk-major, pre-swizzled pack
+//     straight into LDS (each wave's share is one contiguous 4 KB run), two
+//     chunks ahead when the landmarks have no lo parts, else one;
+//   * each thread loads 8 values of one data row of the next chunk into
+//     registers before the products of this one, then splits them into 8 hi
+//     and 8 lo 16-bit values and stores them in that chunk's hi and lo
+//     planes (64-byte rows, 16-byte segments swizzled on row bits 2..3), so
+//     a lane reads its 32 x 32 x 16 operand (8 values of one row) with one
+//     16-byte read;
+//   * the products with the data lo parts are skipped for a chunk in which
+//     every data lo part is zero (they would add exact zeros), decided once
+//     per chunk from flags the splitting waves publish;
+//   * one barrier per chunk: chunk it + 1 is split while chunk it is
+//     multiplied.
+// The 32 x 32 accumulators feed the projection directly: for accumulator
+// register v, lane quarter b holds 16 rows x 1 landmark, the B operand of
+// block b of v_mfma_f32_16x16x1_4b_f32, whose A operand is the W row of
+// that landmark; blocks 0 + 2 and 1 + 3 are added at the end.
+constexpr int S3_THREADS = 512;
+constexpr int S3_XP = BM * 64;   // one part of a data chunk: 128 rows x 32 16-bit values
+constexpr int S3_M = WBN * 64;   // one part of a landmark chunk: 512 x 32 16-bit values
+template <bool HI>
+constexpr int s3_nbuf() { return HI ? 3 : 2; }
+template <bool HI>
+constexpr int s3_buf() { return 2 * S3_XP + (HI ? 1 : 2) * S3_M; }
+template <bool HI>
+constexpr int s3_lds() { return s3_nbuf<HI>() * s3_buf<HI>() + (HI ? 128 : 0); }
+static_assert(s3_lds<true>() <= 163840 && s3_lds<false>() <= 163840, "LDS of the split kernels");
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+// s_waitcnt immediate: vmcnt(vm) (6 bits, split over two fields) and
+// lgkmcnt(lgkm), expcnt left alone
+constexpr int wait_imm(int vm, int lgkm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | (lgkm << 8); }
+
+__device__ inline f16v mfma32(const bf8& a, const bf8& b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f16v mfma32(const h8& a, const h8& b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// byte offset of 16-byte segment g (0..3) of row `row` in a plane of 64-byte rows
+__device__ inline int s3_off(int row, int g) { return row * 64 + ((g ^ ((row >> 2) & 3)) << 4); }
+
+template <int MODE, bool HI>
+__device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict__ X, int64_t ldx,
+                              int nrows, float* __restrict__ Y, int64_t ldy, char* lds) {
+  using V = typename std::conditional<MODE == MODE_BF16, bf8, h8>::type;
+  constexpr int NBUF = s3_nbuf<HI>();
+  constexpr int BUF = s3_buf<HI>();
+  constexpr int MAHEAD = NBUF - 1;  // landmark copies run this many chunks ahead
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 1;   // 64-row half
+  const int wn = wave >> 1;  // 128-landmark quarter of the pass
+  const int l31 = lane & 31;
+  const int half = lane >> 5;
+  const int p = mv.p;
+  const int nch = mv.nchunks;
+  const int64_t l_pad = (int64_t)mv.ntl * BN;
+  const int nst = (int)((l_pad + WBN - 1) / WBN);
+  const int total = nch * nst;
+  const bool xvec = ((((uintptr_t)X) & 15) == 0) && ((ldx * (int64_t)sizeof(float)) % 16 == 0);
+  const bool xfast = xvec && (p % 4 == 0);
+  int* flags = reinterpret_cast<int*>(lds + NBUF * BUF);  // HI: [NBUF][8 waves]
+
+  f16v acc[4][2];    // [landmark block][row block]
+  float ysum[2][8];  // running projection over the passes: [row block][value]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) ysum[j][v] = 0.f;
+  float nacc = 0.f;
+  float xn[2] = {0.f, 0.f};
+
+  // data: thread owns values 8 q8 .. 8 q8 + 7 of row xrow of each chunk;
+  // byte offsets inside the tile are 32-bit, chunk offsets uniform
+  const int xrow = tid >> 2;
+  const int q8 = tid & 3;
+  const char* xbase = reinterpret_cast<const char*>(X);
+  const uint32_t xrow_off = (uint32_t)((int64_t)(xrow < nrows ? xrow : nrows - 1) * ldx * 4);
+  const uint32_t xoff = xrow_off + 32u * (uint32_t)q8;
+  const int sw_off = s3_off(xrow, q8);  // the thread's 16 bytes in a data plane
+  f4 xa, xb;                           // the next chunk's 8 values
+  auto load_x = [&](int ch) {
+    if (xfast) {
+      if (32 * ch + 32 <= p) {
+        const char* cb = xbase + (int64_t)ch * 128;
+        xa = *reinterpret_cast<const f4*>(cb + xoff);
+        xb = *reinterpret_cast<const f4*>(cb + xoff + 16);
+      } else {
+        // last chunk: rows past nrows repeat the last row; a 16-byte piece
+        // past p (p is a multiple of 4) re-reads the row's first values
+        // instead (finite, zeroed by the split), so no read leaves the row
+        const int k = 32 * ch + 8 * q8;
+        xa = *reinterpret_cast<const f4*>(xbase + (k < p ? (int64_t)ch * 128 + xoff : xrow_off));
+        xb = *reinterpret_cast<const f4*>(xbase + (k + 4 < p ? (int64_t)ch * 128 + xoff + 16 : xrow_off));
+      }
+    } else {
+      const int k = 32 * ch + 8 * q8;
+      Seg<float, 4> v0, v1;
+      if (xrow < nrows) {
+        v0 = load_seg<float, 4>(X + (int64_t)xrow * ldx, k, p, xvec);
+        v1 = load_seg<float, 4>(X + (int64_t)xrow * ldx, k + 4, p, xvec);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v0.v[e] = v1.v[e] = 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        xa[e] = v0.v[e];
+        xb[e] = v1.v[e];
+      }
+    }
+  };
+  // split of chunk ch's registers into buffer b; returns whether a data lo
+  // part is nonzero
+  auto split = [&](int ch, int b, bool norms) -> bool {
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x[e] = xa[e];
+      x[4 + e] = xb[e];
+    }
+    if (32 * ch + 32 > p) {
+      const int k0 = 32 * ch + 8 * q8;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = (k0 + e < p) ? x[e] : 0.f;
+    }
+    if (norms) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) nacc = fma(x[e], x[e], nacc);
+    }
+    uint32_t hi[4], lo[4];
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      if constexpr (MODE == MODE_BF16) {
+        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+        typedef float fl2 __attribute__((ext_vector_type(2)));
+        const fl2 xv = {x[e], x[e + 1]};
+        const bf2 h = __builtin_convertvector(xv, bf2);
+        const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+        const fl2 hf = {__builtin_bit_cast(float, hb << 16), __builtin_bit_cast(float, hb & 0xffff0000u)};
+        const fl2 d = {xv[0] - hf[0], xv[1] - hf[1]};
+        hi[e >> 1] = hb;
+        lo[e >> 1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(d, bf2));
+      } else {
+        typedef _Float16 hf2 __attribute__((ext_vector_type(2)));
+        typedef float fl2 __attribute__((ext_vector_type(2)));
+        const fl2 xv = {x[e] * mv.prescale, x[e + 1] * mv.prescale};
+        const hf2 h = __builtin_convertvector(xv, hf2);
+        const fl2 hf = __builtin_convertvector(h, fl2);
+        const fl2 d = {xv[0] - hf[0], xv[1] - hf[1]};
+        hi[e >> 1] = __builtin_bit_cast(uint32_t, h);
+        lo[e >> 1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(d, hf2));
+      }
+    }
+    char* xh = lds + b * BUF + sw_off;
+    *reinterpret_cast<u4*>(xh) = u4{hi[0], hi[1], hi[2], hi[3]};
+    *reinterpret_cast<u4*>(xh + S3_XP) = u4{lo[0], lo[1], lo[2], lo[3]};
+    return ((lo[0] | lo[1]) | (lo[2] | lo[3])) != 0u;
+  };
+  // landmark copies of chunk (s, ch) into buffer b: wave w copies bytes
+  // [4096 w, 4096 w + 4096) of each part
+  const int64_t plane = (int64_t)nch * mv.lsplit * 64;
+  const uint32_t mlane = (uint32_t)lane * 16u;
+  auto dma_m = [&](int s, int ch, int b) {
+    const char* src = reinterpret_cast<const char*>(mv.spack) +
+                      ((int64_t)ch * mv.lsplit + (int64_t)s * WBN) * 64 + wave * 4096;
+    char* mb = lds + b * BUF + 2 * S3_XP + wave * 4096;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + mlane + u * 1024),
+                                       (__attribute__((address_space(3))) void*)(mb + u * 1024), 16, 0, 0);
+    if constexpr (!HI) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + plane + mlane + u * 1024),
+                                         (__attribute__((address_space(3))) void*)(mb + S3_M + u * 1024), 16, 0,
+                                         0);
+    }
+  };
+
+  // operand offsets: row block j and landmark block i add 2048 bytes (32
+  // rows of 64 bytes; the swizzle depends on row bits 2..3 only)
+  const int bo0 = s3_off(64 * wm + l31, half), bo1 = s3_off(64 * wm + l31, 2 + half);
+  const int ao0 = s3_off(128 * wn + l31, half), ao1 = s3_off(128 * wn + l31, 2 + half);
+  // products of the chunk in buffer b: first those with the data hi parts
+  // (hi.hi, then lo.hi when the landmarks have lo parts) for both k-steps,
+  // then, when do_xlo, those with the data lo parts (hi.lo, lo.lo)
+  auto compute = [&](int b, bool do_xlo) {
+    constexpr bool MLO = !HI;
+    const char* base = lds + b * BUF;
+    auto pass = [&](int xplane, bool lo_lo) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const char* pb = base + (ks ? bo1 : bo0) + xplane;
+        const char* pa = base + 2 * S3_XP + (ks ? ao1 : ao0);
+        V bx[2], ah[4], al[4];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bx[j] = *reinterpret_cast<const V*>(pb + 2048 * j);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          ah[i] = *reinterpret_cast<const V*>(pa + 2048 * i);
+          if constexpr (MLO) al[i] = *reinterpret_cast<const V*>(pa + S3_M + 2048 * i);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(ah[i], bx[j], acc[i][j]);
+        if (MLO && lo_lo) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(al[i], bx[j], acc[i][j]);
+        }
+      }
+    };
+    pass(0, true);
+    if (do_xlo) pass(S3_XP, MODE == MODE_BF16);
+  };
+
+  // e = c - |x|^2 + 2 s and Y^T += W^T E^T for the wave's landmarks of pass
+  // s; the pass's projection is then added to the running sum (lane value
+  // (j, k): blocks k >> 2 and 2 + (k >> 2) of the 4-block accumulator).
+  // The c and W rows of landmark block i + 2 are loaded while block i is
+  // projected.
+  auto epilogue = [&](int s) {
+    const float two = 2.0f * mv.postscale;
+    f16v yacc[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) yacc[j][v] = 0.f;
+    const int64_t lb = (int64_t)s * WBN + 128 * wn + 4 * half;
+    const float* cb = reinterpret_cast<const float*>(mv.c) + lb;
+    const float* wb = reinterpret_cast<const float*>(mv.w) + (int64_t)(lane & 15) * mv.ldwt + lb;
+    f4 cw[2][8];
+    auto ld = [&](int i, int slot) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        cw[slot][a] = *reinterpret_cast<const f4*>(cb + 32 * i + 8 * a);
+        cw[slot][4 + a] = *reinterpret_cast<const f4*>(wb + 32 * i + 8 * a);
+      }
+    };
+    ld(0, 0);
+    ld(1, 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int slot = i & 1;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const float e = (cw[slot][v >> 2][v & 3] - xn[j]) + two * acc[i][j][v];
+          yacc[j] = __builtin_amdgcn_mfma_f32_16x16x1f32(cw[slot][4 + (v >> 2)][v & 3], e, yacc[j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+      }
+      if (i + 2 < 4) ld(i + 2, slot);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ysum[j][q] += yacc[j][q] + yacc[j][q + 8];
+  };
+
+  // ---- pipeline ----
+  // iteration it (pass s, chunk ch): data loads of the next chunk
+  // (registers), then the landmark copies of chunk it + MAHEAD (into the
+  // buffer the products of chunk it - 1 read); products of chunk it; split
+  // of the next chunk into its buffer (waits for its data loads only: the
+  // copies were issued after them); wait for the landmark copies of chunk
+  // it + 1; one barrier
+  const int cm = HI ? 4 : 8;  // landmark copies per chunk and wave
+  load_x(0);
+  {
+    int ms = 0, mc = 0;
+    for (int q = 0; q < MAHEAD && q < total; ++q) {
+      dma_m(ms, mc, q);
+      if (++mc == nch) {
+        mc = 0;
+        ++ms;
+      }
+    }
+    const bool nz = split(0, 0, true);
+    if constexpr (HI) {
+      const bool any = __builtin_amdgcn_ballot_w64(nz) != 0;
+      if (lane == 0) flags[wave] = any ? 1 : 0;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(wait_imm(0, 0));
+  raw_barrier();
+  // (s, ch): chunk it; (ns, nc): chunk it + 1; (ms, mc): chunk it + MAHEAD
+  int s = 0, ch = 0, b = 0;
+  int ns = (nch == 1) ? 1 : 0, nc = (nch == 1) ? 0 : 1;
+  int ms = MAHEAD / nch, mc = MAHEAD % nch;
+  for (int it = 0; it < total; ++it) {
+    const bool live = (int64_t)s * WBN + 128 * wn < l_pad;
+    const bool next = it + 1 < total;
+    const int bn = (b + 1 == NBUF) ? 0 : b + 1;
+    if (next) load_x(nc);
+    if (it + MAHEAD < total) dma_m(ms, mc, (b + MAHEAD) % NBUF);
+    bool do_xlo = true;
+    if constexpr (HI) {
+      const int* fb = flags + b * 8;
+      do_xlo = ((fb[0] | fb[1]) | (fb[2] | fb[3]) | (fb[4] | fb[5]) | (fb[6] | fb[7])) != 0;
+    }
+    if (live) compute(b, do_xlo);
+    if (next) {
+      const bool nz = split(nc, bn, ns == 0);
+      if constexpr (HI) {
+        const bool any = __builtin_amdgcn_ballot_w64(nz) != 0;
+        if (lane == 0) flags[bn * 8 + wave] = any ? 1 : 0;
+      }
+    }
+    // the landmark copies of chunk it + 1 have landed once only those of
+    // chunk it + 2 (three buffers) remain; the split's stores are done
+    if (HI && it + 2 < total) __builtin_amdgcn_s_waitcnt(wait_imm(cm, 0));
+    else __builtin_amdgcn_s_waitcnt(wait_imm(0, 0));
+    raw_barrier();
+    if (ch == nch - 1) {
+      if (s == 0) {
+        // row norms (4 threads per row, fixed butterfly) through buffer b,
+        // which nothing touches again before the next iteration's copies
+        float* xnorm = reinterpret_cast<float*>(lds + b * BUF);
+        float t = nacc;
+        t += __shfl_xor(t, 2, 64);
+        t += __shfl_xor(t, 1, 64);
+        if (q8 == 0) xnorm[xrow] = t;
+        __builtin_amdgcn_s_waitcnt(wait_imm(63, 0));
+        raw_barrier();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) xn[j] = xnorm[64 * wm + 32 * j + l31];
+        __builtin_amdgcn_s_waitcnt(wait_imm(63, 0));
+        raw_barrier();
+      }
+      if (live) epilogue(s);
+    }
+    // advance the chunk counters
+    s = ns;
+    ch = nc;
+    b = bn;
+    if (++nc == nch) {
+      nc = 0;
+      ++ns;
+    }
+    if (++mc == nch) {
+      mc = 0;
+      ++ms;
+    }
+  }
+
+  // ---- add the four landmark quarters in order and store ----
+  // lane value (j, k): row 64 h + 32 j + 16 (k >> 2) + (lane & 15), column
+  // 4 (lane >> 4) + (k & 3)
+  __syncthreads();
+  float* ysh = reinterpret_cast<float*>(lds);
+  if (wn > 0) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ysh[((((wn - 1) * 2 + wm) * 2 + j) * 8 + k) * 64 + lane] = ysum[j][k];
+  }
+  __syncthreads();
+  if (wn == 0) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int row = 64 * wm + 32 * j + 16 * (k >> 2) + (lane & 15);
+        const int col = 4 * (lane >> 4) + (k & 3);
+        float val = ysum[j][k];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) val += ysh[(((w * 2 + wm) * 2 + j) * 8 + k) * 64 + lane];
+        if (row < nrows && col < mv.r) Y[(int64_t)row * ldy + col] = val;
+      }
+  }
+  __syncthreads();
+}
+
 // Two waves per SIMD (two blocks per CU) where the registers fit without
 // spilling; the FP64 and wide-output variants keep one.
 template <int MODE, int RB>
@@ -1239,6 +1634,35 @@ __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))
 }
 
 
+// split precisions: the 32 x 32 variant (one 512-thread block per CU)
+template <int MODE, bool HI>
+__global__ __launch_bounds__(S3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_s3(
+    EmbedModelView mv, const float* __restrict__ X, int64_t n, int64_t ldx, float* __restrict__ Y,
+    int64_t ldy) {
+  extern __shared__ __align__(16) char lds[];
+  const int64_t ntiles = (n + BM - 1) / BM;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * BM;
+    const int nrows = (int)((n - row0) < BM ? (n - row0) : BM);
+    embed_tile_s3<MODE, HI>(mv, X + row0 * ldx, ldx, nrows, Y + row0 * ldy, ldy, lds);
+  }
+}
+
+template <int MODE, bool HI>
+__global__ __launch_bounds__(S3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_work_s3(
+    const EmbedModelView* __restrict__ views, const TileWork* __restrict__ work,
+    const int32_t* __restrict__ nwork) {
+  extern __shared__ __align__(16) char lds[];
+  const int nw = nwork[0];
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
+    const TileWork tw = work[w];
+    const EmbedModelView mv = views[tw.model];
+    const float* X = reinterpret_cast<const float*>(tw.x) + tw.row0 * tw.ldx;
+    float* Y = reinterpret_cast<float*>(tw.y) + tw.row0 * tw.ldy;
+    embed_tile_s3<MODE, HI>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+  }
+}
+
 template <int MODE, typename TX, int RB>
 hipError_t launch_t(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                     int64_t ldy, hipStream_t st) {
@@ -1277,14 +1701,32 @@ hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int
   return hipGetLastError();
 }
 
+template <int MODE, bool HI>
+hipError_t launch_s3(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
+                     int64_t ldy, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed_s3<MODE, HI>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, s3_lds<HI>());
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int64_t ntiles = (n + BM - 1) / BM;
+  const int64_t cap = (int64_t)num_cu();
+  const int grid = (int)(ntiles < cap ? ntiles : cap);
+  k_embed_s3<MODE, HI><<<grid, S3_THREADS, s3_lds<HI>(), st>>>(mv, reinterpret_cast<const float*>(X), n, ldx,
+                                                                reinterpret_cast<float*>(Y), ldy);
+  return hipGetLastError();
+}
+
 template <int MODE>
 hipError_t launch_wide(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                        int64_t ldy, hipStream_t st) {
   if constexpr (MODE == MODE_F32)
     return launch_wide_v<MODE, false>(mv, X, n, ldx, Y, ldy, st);
   else
-    return mv.m_lo_zero ? launch_wide_v<MODE, true>(mv, X, n, ldx, Y, ldy, st)
-                        : launch_wide_v<MODE, false>(mv, X, n, ldx, Y, ldy, st);
+    return mv.m_lo_zero ? launch_s3<MODE, true>(mv, X, n, ldx, Y, ldy, st)
+                        : launch_s3<MODE, false>(mv, X, n, ldx, Y, ldy, st);
 }
 
 template <int MODE, typename TX>
@@ -1336,6 +1778,8 @@ EmbedModelView Model::view(int mode) const {
       break;
     case MODE_BF16:
       v.mpack = mbf;
+      v.spack = sbf;
+      v.lsplit = l_split;
       v.w = w32;
       v.ldwt = l_pad;
       v.c = c32;
@@ -1344,6 +1788,8 @@ EmbedModelView Model::view(int mode) const {
       break;
     default:
       v.mpack = mh;
+      v.spack = sh;
+      v.lsplit = l_split;
       v.w = w32;
       v.ldwt = l_pad;
       v.c = c32;
@@ -1389,10 +1835,12 @@ const void* worklist_fn_rb(int rbc) {
     case 0: return reinterpret_cast<const void*>(&k_embed_work<MODE, 1>);
     case 1: return reinterpret_cast<const void*>(&k_embed_work<MODE, 2>);
     case 2: return reinterpret_cast<const void*>(&k_embed_work<MODE, 4>);
-    case kWideClass: return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, false>);
+    case kWideClass:
+      if constexpr (MODE == MODE_F32) return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, false>);
+      else return reinterpret_cast<const void*>(&k_embed_work_s3<MODE, false>);
     default:
       if constexpr (MODE == MODE_F32) return nullptr;
-      else return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, true>);
+      else return reinterpret_cast<const void*>(&k_embed_work_s3<MODE, true>);
   }
 }
 const void* worklist_fn(int mode, int rbc) {
@@ -1412,10 +1860,15 @@ void launch_work_rb(int rbc, int grid, hipStream_t st, const EmbedModelView* v, 
     case 0: k_embed_work<MODE, 1><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
     case 1: k_embed_work<MODE, 2><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
     case 2: k_embed_work<MODE, 4><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
-    case kWideClass: k_embed_work_wide<MODE, false><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw); break;
+    case kWideClass:
+      if constexpr (MODE == MODE_F32)
+        k_embed_work_wide<MODE, false><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw);
+      else
+        k_embed_work_s3<MODE, false><<<grid, S3_THREADS, s3_lds<false>(), st>>>(v, w, nw);
+      break;
     default:
       if constexpr (MODE != MODE_F32)
-        k_embed_work_wide<MODE, true><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw);
+        k_embed_work_s3<MODE, true><<<grid, S3_THREADS, s3_lds<true>(), st>>>(v, w, nw);
       break;
   }
 }
@@ -1439,8 +1892,10 @@ mds_status prepare_embed_worklist(int mode, int rbc) {
   const void* fn = worklist_fn(mode, rbc);
   if (!fn) return set_error(MDS_ERR_INVALID_ARG, "serving supports FP32 and split precisions");
   if (!g_work_attr[mode][rbc]) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       rbc >= kWideClass ? WLDS_BYTES : LDS_BYTES);
+    const int bytes = rbc < kWideClass ? LDS_BYTES
+                      : mode == MODE_F32 ? WLDS_BYTES
+                      : rbc == kWideHiClass ? s3_lds<true>() : s3_lds<false>();
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
     g_work_attr[mode][rbc] = true;
   }

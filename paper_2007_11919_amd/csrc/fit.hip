@@ -665,9 +665,14 @@ __global__ __launch_bounds__(256) void k_scale(const double* __restrict__ rowmax
 
 // Operand packs of the embed kernels (see embed.hip for the layout):
 // FP32: row i, chunk ch -> 32 floats; split modes: 32 hi then 32 lo.
+// Chunk-major split packs (sbf, sh): plane P (hi, lo), chunk ch, landmark i
+// -> 64 bytes at ((P nch + ch) l_split + i) * 64, whose 16-byte segment g
+// (values 8 g .. 8 g + 7 of the chunk) sits at position g ^ ((i >> 2) & 3),
+// the order in which the kernels keep a landmark row in LDS.
 __global__ void k_pack32(const double* __restrict__ M, int64_t ldm, int64_t l_pad, int64_t p,
                          int nch, float* __restrict__ m32, uint16_t* __restrict__ mbf,
-                         uint16_t* __restrict__ mh, const float* __restrict__ scales,
+                         uint16_t* __restrict__ mh, uint16_t* __restrict__ sbf,
+                         uint16_t* __restrict__ sh, int64_t l_split, const float* __restrict__ scales,
                          int* __restrict__ lo_flags) {
   const float prescale = scales[0];
   const int64_t total = l_pad * (int64_t)nch * 32;
@@ -696,6 +701,12 @@ __global__ void k_pack32(const double* __restrict__ M, int64_t ldm, int64_t l_pa
     const _Float16 hl = (_Float16)(xs - (float)hh);
     mh[base + kk] = __builtin_bit_cast(uint16_t, hh);
     mh[base + 32 + kk] = __builtin_bit_cast(uint16_t, hl);
+    const int64_t plane = (int64_t)nch * l_split * 32;
+    const int64_t soff = ((int64_t)ch * l_split + row) * 32 + (((kk >> 3) ^ ((row >> 2) & 3)) << 3) + (kk & 7);
+    sbf[soff] = __builtin_bit_cast(uint16_t, bh);
+    sbf[plane + soff] = __builtin_bit_cast(uint16_t, bl);
+    sh[soff] = __builtin_bit_cast(uint16_t, hh);
+    sh[plane + soff] = __builtin_bit_cast(uint16_t, hl);
     if ((float)bl != 0.0f) lo_flags[0] = 1;
     if ((float)hl != 0.0f) lo_flags[1] = 1;
   }
@@ -777,6 +788,10 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   const size_t o32 = lay.take(sizeof(float) * l_split * nch32 * 32);
   const size_t obf = lay.take(sizeof(uint16_t) * l_split * nch32 * 64);
   const size_t oh = lay.take(sizeof(uint16_t) * l_split * nch32 * 64);
+  // the same parts chunk-major for the 32 x 32 split kernels: a hi plane
+  // then a lo plane, each nch32 x l_split x 32 values
+  const size_t osbf = lay.take(sizeof(uint16_t) * l_split * nch32 * 64);
+  const size_t osh = lay.take(sizeof(uint16_t) * l_split * nch32 * 64);
   const size_t ow32 = lay.take(sizeof(float) * l_pad * ldw);
   const size_t ow64 = lay.take(sizeof(double) * l_pad * ldw);
   const size_t oc32 = lay.take(sizeof(float) * l_pad);
@@ -795,6 +810,9 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   m.m32 = b + o32;
   m.mbf = b + obf;
   m.mh = b + oh;
+  m.sbf = b + osbf;
+  m.sh = b + osh;
+  m.l_split = l_split;
   m.w32 = b + ow32;
   m.w64 = b + ow64;
   m.c32 = b + oc32;
@@ -1052,7 +1070,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     const int64_t total = l_pad * (int64_t)nch32 * 32;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
     k_pack32<<<grid, 256, 0, st>>>((const double*)m.m64, ldm, l_pad, p, nch32, (float*)m.m32,
-                                   (uint16_t*)m.mbf, (uint16_t*)m.mh, scales, ctrl + 10);
+                                   (uint16_t*)m.mbf, (uint16_t*)m.mh, (uint16_t*)m.sbf, (uint16_t*)m.sh,
+                                   m.l_split, scales, ctrl + 10);
     // landmark chunks for the affine map (each wave walks a few landmarks,
     // so the loop is not a chain of memory latencies): up to 64, partials
     // within 64 MB

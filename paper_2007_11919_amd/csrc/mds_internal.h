@@ -62,6 +62,8 @@ struct EmbedModelView {
   float prescale;      // split FP16: data scaled by 2^s before splitting
   float postscale;     // split FP16: 2^-2s applied to the dot products
   int64_t ldwt;        // leading dimension of the FP32 weights
+  const void* spack;   // split modes: chunk-major hi and lo planes (Model::sbf / sh)
+  int64_t lsplit;      // landmark rows of each chunk in spack
 };
 
 // One row tile of one request, for the persistent serving kernel.
@@ -89,6 +91,9 @@ struct Model {
   void* m32 = nullptr;    // round_up(l_pad, kSplitPackRows) x nchunks32 x 32 floats
   void* mbf = nullptr;    // round_up(l_pad, kSplitPackRows) x nchunks32 x (32 hi + 32 lo) bf16
   void* mh = nullptr;     // same for FP16 (scaled)
+  void* sbf = nullptr;    // chunk-major BF16 parts: hi plane, lo plane (fit.hip k_pack32)
+  void* sh = nullptr;     // same for FP16 (scaled)
+  int64_t l_split = 0;    // round_up(l_pad, kSplitPackRows)
   void* w32 = nullptr;    // 16rb x l_pad float (column-major: output column, landmark)
   void* w64 = nullptr;    // l_pad x 16rb double
   void* c32 = nullptr;    // l_pad float
