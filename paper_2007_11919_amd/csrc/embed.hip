@@ -1252,20 +1252,23 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
   const uint32_t xrow_off = (uint32_t)((int64_t)(xrow < nrows ? xrow : nrows - 1) * ldx * 4);
   const uint32_t xoff = xrow_off + 32u * (uint32_t)q8;
   const int sw_off = s3_off(xrow, q8);  // the thread's 16 bytes in a data plane
-  f4 xa, xb;                           // the next chunk's 8 values
-  auto load_x = [&](int ch) {
+  f4 xa[2], xb[2];                     // 8 values of two chunks in flight
+  auto load_x = [&](int ch, auto slot_tag) {
+    constexpr int SL = decltype(slot_tag)::value;
+    f4& xa_ = xa[SL];
+    f4& xb_ = xb[SL];
     if (xfast) {
       if (32 * ch + 32 <= p) {
         const char* cb = xbase + (int64_t)ch * 128;
-        xa = *reinterpret_cast<const f4*>(cb + xoff);
-        xb = *reinterpret_cast<const f4*>(cb + xoff + 16);
+        xa_ = *reinterpret_cast<const f4*>(cb + xoff);
+        xb_ = *reinterpret_cast<const f4*>(cb + xoff + 16);
       } else {
         // last chunk: rows past nrows repeat the last row; a 16-byte piece
         // past p (p is a multiple of 4) re-reads the row's first values
         // instead (finite, zeroed by the split), so no read leaves the row
         const int k = 32 * ch + 8 * q8;
-        xa = *reinterpret_cast<const f4*>(xbase + (k < p ? (int64_t)ch * 128 + xoff : xrow_off));
-        xb = *reinterpret_cast<const f4*>(xbase + (k + 4 < p ? (int64_t)ch * 128 + xoff + 16 : xrow_off));
+        xa_ = *reinterpret_cast<const f4*>(xbase + (k < p ? (int64_t)ch * 128 + xoff : xrow_off));
+        xb_ = *reinterpret_cast<const f4*>(xbase + (k + 4 < p ? (int64_t)ch * 128 + xoff + 16 : xrow_off));
       }
     } else {
       const int k = 32 * ch + 8 * q8;
@@ -1279,19 +1282,20 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        xa[e] = v0.v[e];
-        xb[e] = v1.v[e];
+        xa_[e] = v0.v[e];
+        xb_[e] = v1.v[e];
       }
     }
   };
   // split of chunk ch's registers into buffer b; returns whether a data lo
   // part is nonzero
-  auto split = [&](int ch, int b, bool norms) -> bool {
+  auto split = [&](int ch, int b, bool norms, auto slot_tag) -> bool {
+    constexpr int SL = decltype(slot_tag)::value;
     float x[8];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      x[e] = xa[e];
-      x[4 + e] = xb[e];
+      x[e] = xa[SL][e];
+      x[4 + e] = xb[SL][e];
     }
     if (32 * ch + 32 > p) {
       const int k0 = 32 * ch + 8 * q8;
@@ -1438,14 +1442,15 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
   };
 
   // ---- pipeline ----
-  // iteration it (pass s, chunk ch): data loads of the next chunk
-  // (registers), then the landmark copies of chunk it + MAHEAD (into the
-  // buffer the products of chunk it - 1 read); products of chunk it; split
-  // of the next chunk into its buffer (waits for its data loads only: the
-  // copies were issued after them); wait for the landmark copies of chunk
-  // it + 1; one barrier
+  // iteration it (pass s, chunk ch): landmark copies of chunk it + MAHEAD
+  // (into the buffer the products of chunk it - 1 read), then data loads of
+  // chunk it + 2 into the register slot chunk it used; products of chunk
+  // it; split of chunk it + 1 (loaded two iterations back) into its buffer;
+  // wait for the landmark copies of chunk it + 1; one barrier.  The loop is
+  // unrolled by two so that the register slots are fixed.
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
   const int cm = HI ? 4 : 8;  // landmark copies per chunk and wave
-  load_x(0);
   {
     int ms = 0, mc = 0;
     for (int q = 0; q < MAHEAD && q < total; ++q) {
@@ -1455,7 +1460,11 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
         ++ms;
       }
     }
-    const bool nz = split(0, 0, true);
+  }
+  load_x(0, S0{});
+  if (total > 1) load_x(1 % nch, S1{});
+  {
+    const bool nz = split(0, 0, true, S0{});
     if constexpr (HI) {
       const bool any = __builtin_amdgcn_ballot_w64(nz) != 0;
       if (lane == 0) flags[wave] = any ? 1 : 0;
@@ -1463,16 +1472,20 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
   }
   __builtin_amdgcn_s_waitcnt(wait_imm(0, 0));
   raw_barrier();
-  // (s, ch): chunk it; (ns, nc): chunk it + 1; (ms, mc): chunk it + MAHEAD
+  // (s, ch): chunk it; (ns, nc): chunk it + 1; (ms, mc): chunk it + MAHEAD;
+  // lc: the chunk (within its pass) of chunk it + 2
   int s = 0, ch = 0, b = 0;
   int ns = (nch == 1) ? 1 : 0, nc = (nch == 1) ? 0 : 1;
   int ms = MAHEAD / nch, mc = MAHEAD % nch;
-  for (int it = 0; it < total; ++it) {
+  int lc = 2 % nch;
+  auto step = [&](int it, auto cur) {
+    using SC = decltype(cur);
+    using SN = std::integral_constant<int, 1 - SC::value>;
     const bool live = (int64_t)s * WBN + 128 * wn < l_pad;
     const bool next = it + 1 < total;
     const int bn = (b + 1 == NBUF) ? 0 : b + 1;
-    if (next) load_x(nc);
     if (it + MAHEAD < total) dma_m(ms, mc, (b + MAHEAD) % NBUF);
+    if (it + 2 < total) load_x(lc, SC{});
     bool do_xlo = true;
     if constexpr (HI) {
       const int* fb = flags + b * 8;
@@ -1480,15 +1493,18 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
     }
     if (live) compute(b, do_xlo);
     if (next) {
-      const bool nz = split(nc, bn, ns == 0);
+      const bool nz = split(nc, bn, ns == 0, SN{});
       if constexpr (HI) {
         const bool any = __builtin_amdgcn_ballot_w64(nz) != 0;
         if (lane == 0) flags[bn * 8 + wave] = any ? 1 : 0;
       }
     }
-    // the landmark copies of chunk it + 1 have landed once only those of
-    // chunk it + 2 (three buffers) remain; the split's stores are done
-    if (HI && it + 2 < total) __builtin_amdgcn_s_waitcnt(wait_imm(cm, 0));
+    // the landmark copies of chunk it + 1 have landed once at most the
+    // later memory operations remain: (three buffers) data loads of chunks
+    // it + 1 and it + 2 and copies of chunk it + 2, (two buffers) data
+    // loads of chunk it + 2; the split's stores are done
+    if (HI && it + 2 < total) __builtin_amdgcn_s_waitcnt(wait_imm(cm + 4, 0));
+    else if (!HI && it + 2 < total) __builtin_amdgcn_s_waitcnt(wait_imm(2, 0));
     else __builtin_amdgcn_s_waitcnt(wait_imm(0, 0));
     raw_barrier();
     if (ch == nch - 1) {
@@ -1521,6 +1537,11 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
       mc = 0;
       ++ms;
     }
+    if (++lc == nch) lc = 0;
+  };
+  for (int it = 0; it < total; it += 2) {
+    step(it, S0{});
+    if (it + 1 < total) step(it + 1, S1{});
   }
 
   // ---- add the four landmark quarters in order and store ----
