@@ -26,8 +26,10 @@
 // The per-row reduction order is fixed (landmark tiles in order, then the
 // two landmark halves of a block in order), so a row's result does not
 // depend on the batch it arrives in.  Models with one 16-column output
-// block run the 512-landmark variant further down when it pays (the choice
-// is a function of the model alone).  In FP32 the 16-value k-block holding
+// block run a 512-landmark variant further down when it pays (the choice
+// is a function of the model alone): embed_tile_wide in FP32, and in the
+// split precisions embed_tile_s3, which uses 32 x 32 x 16 products on
+// data and landmark parts kept in separate hi and lo planes.  In FP32 the 16-value k-block holding
 // value p - 1 is stored transposed in the landmark pack and in LDS, so the
 // products past p can be skipped.
 #include <hip/hip_runtime.h>
@@ -453,29 +455,26 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
   __syncthreads();
 }
 
-// ---- 512 landmarks per pass over the row tile (FP32, and split
-// precisions at large p)
+// ---- FP32 with 512 landmarks per pass over the row tile ----
 // The 128-landmark kernel moves one 128 x 32 data chunk and one 128 x 32
 // landmark chunk through LDS per 128 x 128 x 32 block of products; its two
 // blocks per CU tend to run in phase, so the copies and barriers add to the
 // MFMA time instead of hiding under it.  With p in the hundreds a 128-row
 // tile of X is also too large to stay in L2 while the block walks the
-// landmarks, so every landmark tile re-reads (and, split, re-splits) it.
-// This variant keeps the 128-row tile but walks the landmarks WBN = 512 at a
-// time: eight waves as 2 row halves x 4 landmark quarters, each 64 rows x
-// 128 landmarks of accumulators, so a chunk copy feeds twice the products
-// and X is read a quarter as often.  One chunk buffer (X 16 KB + landmarks
-// 64 KB; FP32 values or hi/lo halves) is double-buffered, which fills the
-// 160 KB of LDS; 16-byte segments are XOR-swizzled by row instead of
-// padded, and the landmark operands are copied from memory straight into
-// LDS (the FP32 and split packs are allocated to a multiple of WBN rows,
-// zero past l_pad); in FP32, aligned data chunks without a ragged k-block
-// are copied the same way.  The split forms pass the row norms once through
-// the buffer just consumed; in FP32 each wave sums them from the operands
+// landmarks, so every landmark tile re-reads it.  This variant keeps the
+// 128-row tile but walks the landmarks WBN = 512 at a time: eight waves as
+// 2 row halves x 4 landmark quarters, each 64 rows x 128 landmarks of
+// accumulators, so a chunk copy feeds twice the products and X is read a
+// quarter as often.  One chunk buffer (X 16 KB + landmarks 64 KB) is
+// double-buffered, which fills the 160 KB of LDS; 16-byte segments are
+// XOR-swizzled by row instead of padded, and the landmark operands are
+// copied from memory straight into LDS (the FP32 pack is allocated to a
+// multiple of WBN rows, zero past l_pad), as are aligned data chunks
+// without a ragged k-block.  Each wave sums the row norms from the operands
 // it reads.  The quarters are added in order at the end.  The landmark
 // order of the sums differs from the 128-landmark variant, so each model
-// and precision always runs the same variant (plain and serving launches
-// alike).
+// always runs the same variant (plain and serving launches alike).  The
+// split precisions use the same passes of 512 landmarks in embed_tile_s3.
 constexpr int WBN = 512;
 constexpr int WTHREADS = 512;
 constexpr int WX_BYTES = BM * CHUNK_BYTES;
@@ -490,13 +489,11 @@ constexpr int kWaitVm0 = 0x0F70;
 // XOR with bits 1..3 of the row puts the 16 rows read by 16 lanes (row
 // pairs share a 256-byte line) on distinct 16-byte slots
 __device__ inline int swz(int row, int seg) { return (seg ^ ((row >> 1) & 7)) << 4; }
-// the same for 64-byte rows (four segments): bits 2..3 of the row
-__device__ inline int swz64(int row, int seg) { return (seg ^ ((row >> 2) & 3)) << 4; }
 
 template <int MODE>
 __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restrict__ X, int64_t ldx,
                                 int nrows, float* __restrict__ Y, int64_t ldy, char* lds) {
-  using V = typename std::conditional<MODE == MODE_BF16, bf8, h8>::type;
+  static_assert(MODE == MODE_F32, "the split precisions run embed_tile_s3");
   constexpr int E = 4;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -512,7 +509,6 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   const int total = nch * nst;
   const bool xvec = ((((uintptr_t)X) & 15) == 0) && ((ldx * (int64_t)sizeof(float)) % 16 == 0);
   const bool xfast = xvec && (p % E == 0);
-  const bool do_mlo = !mv.m_lo_zero;
 
   // loader mapping: X rows lrow + 64 u (u < 2), 16-byte slot lseg
   const int lrow = tid >> 3;
@@ -526,10 +522,9 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
 #pragma unroll
   for (int b = 0; b < 4; ++b) yacc[b] = f4{0, 0, 0, 0};
-  float nacc[2] = {0.f, 0.f};
   float xn[4] = {0.f, 0.f, 0.f, 0.f};
   Seg<float, E> xr[2];
-  // FP32: each wave sums the squares of the data operands it reads in the
+  // each wave sums the squares of the data operands it reads in the
   // first pass (lane (lr, g) holds a quarter of row 16 j + lr), so the row
   // norms need no exchange, whichever way a chunk reached LDS
   float nrm[4] = {0.f, 0.f, 0.f, 0.f};
@@ -552,7 +547,7 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
                                        16, 0, 0);
   };
 
-  // FP32 data chunks without a ragged k-block also go straight to LDS when
+  // Data chunks without a ragged k-block also go straight to LDS when
   // the rows are 16-byte aligned: wave copy u fills rows 64 u + 8 w .. + 8
   // with the same lane mapping as the landmark copies.  Rows past nrows
   // repeat the last row (their results are not stored); a segment that
@@ -562,7 +557,7 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   const int xdseg = ((lane & 7) ^ ((4 * (wave & 1) + (lane >> 4)) & 7)) * E;
   // the chunk holds no computed k-block with values past p
   auto x_direct = [&](int ch) {
-    if (MODE != MODE_F32 || !xfast) return false;
+    if (!xfast) return false;
     const int r0 = p - ch * 32, r1 = r0 - 16;
     return !(r0 > 0 && r0 < 16) && !(r1 > 0 && r1 < 16);
   };
@@ -609,60 +604,26 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
       }
     }
   };
-  auto accumulate_norm = [&]() {
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int i = 0; i < E; ++i) nacc[u] = fma(xr[u].v[i], xr[u].v[i], nacc[u]);
-  };
   auto store_chunk = [&](int buf, int ch) {
     char* xb = lds + buf * WBUF_BYTES;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int row = lrow + 64 * u;
-      if constexpr (MODE == MODE_F32) {
-        if (p - (ch * 32 + (lseg >> 2) * 16) < 16) {
-          // tail k-block, transposed: value c of this segment goes to
-          // segment 4 (lseg / 4) + c, slot lseg % 4
+      if (p - (ch * 32 + (lseg >> 2) * 16) < 16) {
+        // tail k-block, transposed: value c of this segment goes to
+        // segment 4 (lseg / 4) + c, slot lseg % 4
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            *reinterpret_cast<float*>(xb + row * CHUNK_BYTES + swz(row, 4 * (lseg >> 2) + c) + 4 * (lseg & 3)) =
-                xr[u].v[c];
-        } else {
-          u4 v;
-          __builtin_memcpy(&v, &xr[u], 16);
-          *reinterpret_cast<u4*>(xb + row * CHUNK_BYTES + swz(row, lseg)) = v;
-        }
-        continue;
+        for (int c = 0; c < 4; ++c)
+          *reinterpret_cast<float*>(xb + row * CHUNK_BYTES + swz(row, 4 * (lseg >> 2) + c) + 4 * (lseg & 3)) =
+              xr[u].v[c];
+      } else {
+        u4 v;
+        __builtin_memcpy(&v, &xr[u], 16);
+        *reinterpret_cast<u4*>(xb + row * CHUNK_BYTES + swz(row, lseg)) = v;
       }
-      uint16_t hi[4], lo[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float x = xr[u].v[i];
-        if constexpr (MODE == MODE_BF16) {
-          const __bf16 h = (__bf16)x;
-          const __bf16 lw = (__bf16)(x - (float)h);
-          hi[i] = __builtin_bit_cast(uint16_t, h);
-          lo[i] = __builtin_bit_cast(uint16_t, lw);
-        } else {
-          x *= mv.prescale;
-          const _Float16 h = (_Float16)x;
-          const _Float16 lw = (_Float16)(x - (float)h);
-          hi[i] = __builtin_bit_cast(uint16_t, h);
-          lo[i] = __builtin_bit_cast(uint16_t, lw);
-        }
-      }
-      const u2 hv = {(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
-      const u2 lv = {(uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
-      // the 8 hi bytes of elements 4 lseg.. sit in hi segment lseg / 2
-      char* rowp = xb + row * CHUNK_BYTES + (lseg & 1) * 8;
-      *reinterpret_cast<u2*>(rowp + swz(row, lseg >> 1)) = hv;
-      *reinterpret_cast<u2*>(rowp + swz(row, 4 + (lseg >> 1))) = lv;
     }
   };
-  // The products with the data lo parts are skipped when every lo part the
-  // wave holds is zero (integer-valued data): they would add exact zeros.
-  // FP32: lane group g holds values 4 g .. 4 g + 3 of a k-block (the
+  // Lane group g holds values 4 g .. 4 g + 3 of a k-block (the
   // tail k-block is stored transposed, so that product jj holds values
   // 4 jj .. 4 jj + 3 there and the products past p are skipped)
   auto compute_chunk_f32 = [&](int buf, int ch, bool norms) {
@@ -697,45 +658,9 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
       }
     }
   };
-  auto compute_chunk = [&](int buf) {
-    const char* xb = lds + buf * WBUF_BYTES;
-    const char* mb = xb + WX_BYTES;
-    V bh[4], bl[4];
-    bool lo_nz = false;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = 64 * wm + 16 * j + lr;
-      bh[j] = *reinterpret_cast<const V*>(xb + row * CHUNK_BYTES + swz(row, lg));
-      bl[j] = *reinterpret_cast<const V*>(xb + row * CHUNK_BYTES + swz(row, 4 + lg));
-      const u4 bits = __builtin_bit_cast(u4, bl[j]);
-      lo_nz |= (bits[0] | bits[1] | bits[2] | bits[3]) != 0u;
-    }
-    const bool do_xlo = __builtin_amdgcn_ballot_w64(lo_nz) != 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int lm = 128 * wn + 16 * i + lr;
-      const V ah = *reinterpret_cast<const V*>(mb + lm * CHUNK_BYTES + swz(lm, lg));
-      V al;
-      if (do_mlo) al = *reinterpret_cast<const V*>(mb + lm * CHUNK_BYTES + swz(lm, 4 + lg));
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if constexpr (MODE == MODE_BF16) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-          if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-          if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-          if (do_mlo && do_xlo)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl[j], acc[i][j], 0, 0, 0);
-        } else {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
-          if (do_mlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
-          if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc[i][j], 0, 0, 0);
-        }
-      }
-    }
-  };
   // e = c - |x|^2 + 2 s and Y^T += W^T E^T for the wave's quarter of super tile s
   auto epilogue = [&](int s) {
-    const float two = 2.0f * mv.postscale;
+    const float two = 2.0f;
     // (formed here rather than kept live across the chunk loop)
     const float* cb = reinterpret_cast<const float*>(mv.c) + (int64_t)s * WBN + 128 * wn + 4 * lg;
     const float* wb =
@@ -764,7 +689,6 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
     dma_x(0, 0);
   } else {
     load_chunk(0);
-    if constexpr (MODE != MODE_F32) accumulate_norm();
     store_chunk(0, 0);
   }
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
@@ -785,48 +709,21 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
       else
         load_chunk(nchn);
     }
-    if (live) {
-      if constexpr (MODE == MODE_F32)
-        compute_chunk_f32(buf, ch, s == 0);
-      else
-        compute_chunk(buf);
-    }
-    if (has_next && !next_direct) {
-      if constexpr (MODE != MODE_F32)
-        if (nsn == 0) accumulate_norm();
-      store_chunk(buf ^ 1, nchn);
-    }
+    if (live) compute_chunk_f32(buf, ch, s == 0);
+    if (has_next && !next_direct) store_chunk(buf ^ 1, nchn);
     const bool tile_end = (ch == nch - 1);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
     if (tile_end) {
       if (s == 0) {
-        if constexpr (MODE == MODE_F32) {
-          // fixed butterfly over the four lane groups: every lane of a row
-          // gets the same bits
+        // fixed butterfly over the four lane groups: every lane of a row
+        // gets the same bits
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            float t = nrm[j];
-            t += __shfl_xor(t, 16, 64);
-            t += __shfl_xor(t, 32, 64);
-            xn[j] = t;
-          }
-        } else {
-          // row norms (8 lanes per row, fixed butterfly) through buffer buf,
-          // which nobody reads or writes again before the next store into it
-          float* xnorm = reinterpret_cast<float*>(lds + buf * WBUF_BYTES);
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            float t = nacc[u];
-            t += __shfl_xor(t, 4, 64);
-            t += __shfl_xor(t, 2, 64);
-            t += __shfl_xor(t, 1, 64);
-            if (lseg == 0) xnorm[lrow + 64 * u] = t;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int j = 0; j < 4; ++j) xn[j] = xnorm[64 * wm + 16 * j + lr];
-          __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+          float t = nrm[j];
+          t += __shfl_xor(t, 16, 64);
+          t += __shfl_xor(t, 32, 64);
+          xn[j] = t;
         }
       }
       if (live) epilogue(s);
@@ -863,297 +760,15 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   __syncthreads();
 }
 
-// ---- the same at large p when every landmark lo part is zero ----
-// (integer-valued landmarks, the usual case for image data).  The landmark
-// operands are then hi parts only, 32 KB per 512 x 32 chunk, which leaves
-// room for three chunk buffers (X 16 KB + landmarks 32 KB each), so the
-// copies run two chunks ahead of the MFMAs: data rows and landmarks both go
-// from memory straight into LDS.  Each thread then splits its own two
-// 16-byte data segments in place (4 FP32 values -> 4 hi + 4 lo 16-bit
-// values in the same 16 bytes), so a lane reading the two segments of its
-// MFMA fragment gets hi and lo without further work.  Barriers are raw
-// s_barrier with an explicit wait that leaves the newest chunk's copies in
-// flight; a compiler memory barrier keeps LDS accesses on their side of it.
-constexpr int WH_X = BM * CHUNK_BYTES;  // 128 rows x 32 values
-constexpr int WH_ROW = 64;              // landmark hi part of one chunk
-constexpr int WH_BUF = WH_X + WBN * WH_ROW;
-constexpr int WH_NBUF = 3;
-static_assert(WH_NBUF * WH_BUF <= WLDS_BYTES, "three buffers fit the LDS of the wide variant");
-// s_waitcnt immediates: lgkmcnt(0) with vmcnt(n)
-constexpr int kWaitLgkVm(int n) { return 0x0070 | n; }
-constexpr int kWhCopiesFast = 6;  // copies per chunk and wave: 2 data + 4 landmark
-constexpr int kWhCopiesSlow = 4;  // landmark copies only (data rows via registers)
-
+// Barriers of the split kernel are raw s_barrier with an explicit wait that
+// leaves the newest copies in flight; a compiler memory barrier keeps LDS
+// accesses on their side of it.
 __device__ inline void raw_barrier() {
   asm volatile("" ::: "memory");
   __builtin_amdgcn_sched_barrier(0);
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_sched_barrier(0);
   asm volatile("" ::: "memory");
-}
-
-template <int MODE>
-__device__ void embed_tile_wide_h(const EmbedModelView& mv, const float* __restrict__ X, int64_t ldx,
-                                  int nrows, float* __restrict__ Y, int64_t ldy, char* lds) {
-  using V = typename std::conditional<MODE == MODE_BF16, bf8, h8>::type;
-  constexpr int E = 4;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave & 1;   // 64-row half
-  const int wn = wave >> 1;  // 128-landmark quarter
-  const int lr = lane & 15;
-  const int lg = lane >> 4;
-  const int p = mv.p;
-  const int nch = mv.nchunks;
-  const int64_t l_pad = (int64_t)mv.ntl * BN;
-  const int nst = (int)((l_pad + WBN - 1) / WBN);
-  const int total = nch * nst;
-  const bool xvec = ((((uintptr_t)X) & 15) == 0) && ((ldx * (int64_t)sizeof(float)) % 16 == 0);
-  const bool xfast = xvec && (p % E == 0);
-
-  f4 acc[8][4];  // [landmark block][row block]
-  f4 yacc[4];
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
-#pragma unroll
-  for (int b = 0; b < 4; ++b) yacc[b] = f4{0, 0, 0, 0};
-  float nacc[2] = {0.f, 0.f};
-  float xn[4] = {0.f, 0.f, 0.f, 0.f};
-
-  // data copies (fast path): wave copy u fills rows 64 u + 8 w .. + 8, lane
-  // L the physical segment L % 8 of row L / 8 (logical (L % 8) ^ ((row / 2) % 8));
-  // rows past nrows repeat the last row and columns past p re-read the
-  // row's first columns (both finite; zeroed by the split)
-  const int xsub = lane >> 3;
-  const int xseg = (lane & 7) ^ ((4 * (wave & 1) + (lane >> 4)) & 7);
-  const float* xsrc[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int row = 64 * u + 8 * wave + xsub;
-    xsrc[u] = X + (int64_t)(row < nrows ? row : nrows - 1) * ldx + xseg * E;
-  }
-  // landmark copies: wave copy u fills landmark rows 128 u + 16 w .. + 16
-  // (64 bytes each), lane L the physical segment L % 4 of row L / 4
-  // (logical (L % 4) ^ ((row / 4) % 4)); the hi half of each packed chunk
-  const int64_t mrow_bytes = (int64_t)nch * CHUNK_BYTES;
-  const char* mlane = reinterpret_cast<const char*>(mv.mpack) +
-                      (int64_t)(16 * wave + (lane >> 2)) * mrow_bytes + (((lane & 3) ^ ((lane >> 4) & 3)) << 4);
-  // the split: thread owns logical segment lseg of rows lrow + 64 u
-  const int lrow = tid >> 3;
-  const int lseg = tid & 7;
-
-  auto issue = [&](int it, int b) {
-    const int s = it / nch, ch = it - (it / nch) * nch;
-    char* xb = lds + b * WH_BUF;
-    char* mb = xb + WH_X;
-    if (xfast) {
-      const int64_t koff = ((int64_t)ch * 32 + xseg * E < p) ? (int64_t)ch * 32 : 0;
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(xsrc[u] + koff),
-                                         (__attribute__((address_space(3))) void*)(xb + (64 * u + 8 * wave) * CHUNK_BYTES),
-                                         16, 0, 0);
-    } else {
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int row = lrow + 64 * u;
-        Seg<float, E> v;
-        if (row < nrows) {
-          v = load_seg<float, E>(X + (int64_t)row * ldx, (int64_t)ch * 32 + lseg * E, p, xvec);
-        } else {
-#pragma unroll
-          for (int i = 0; i < E; ++i) v.v[i] = 0.f;
-        }
-        *reinterpret_cast<Seg<float, E>*>(xb + row * CHUNK_BYTES + swz(row, lseg)) = v;
-      }
-    }
-    const char* msrc = mlane + (int64_t)s * WBN * mrow_bytes + (int64_t)ch * CHUNK_BYTES;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(msrc + (int64_t)(128 * u) * mrow_bytes),
-                                       (__attribute__((address_space(3))) void*)(mb + (128 * u + 16 * wave) * WH_ROW),
-                                       16, 0, 0);
-  };
-
-  // in-place split of the thread's two segments of chunk (s, ch) in buffer b
-  auto split_chunk = [&](int b, int ch, bool norms) {
-    char* xb = lds + b * WH_BUF;
-    const int k0 = ch * 32 + lseg * E;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int row = lrow + 64 * u;
-      char* sp = xb + row * CHUNK_BYTES + swz(row, lseg);
-      f4 x = *reinterpret_cast<const f4*>(sp);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) x[e] = (k0 + e < p) ? x[e] : 0.f;
-      if (norms) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) nacc[u] = fma(x[e], x[e], nacc[u]);
-      }
-      uint16_t hi[4], lo[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if constexpr (MODE == MODE_BF16) {
-          const __bf16 h = (__bf16)x[e];
-          const __bf16 lw = (__bf16)(x[e] - (float)h);
-          hi[e] = __builtin_bit_cast(uint16_t, h);
-          lo[e] = __builtin_bit_cast(uint16_t, lw);
-        } else {
-          const float xs = x[e] * mv.prescale;
-          const _Float16 h = (_Float16)xs;
-          const _Float16 lw = (_Float16)(xs - (float)h);
-          hi[e] = __builtin_bit_cast(uint16_t, h);
-          lo[e] = __builtin_bit_cast(uint16_t, lw);
-        }
-      }
-      const u4 packed = {(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16),
-                         (uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
-      *reinterpret_cast<u4*>(sp) = packed;
-    }
-  };
-
-  // The products with the data lo parts are skipped when every lo part the
-  // wave holds is zero: they would add exact zeros.
-  auto compute_chunk = [&](int b) {
-    const char* xb = lds + b * WH_BUF;
-    const char* mb = xb + WH_X;
-    V bh[4], bl[4];
-    uint32_t lo_or = 0u;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = 64 * wm + 16 * j + lr;
-      const u4 sa = *reinterpret_cast<const u4*>(xb + row * CHUNK_BYTES + swz(row, 2 * lg));
-      const u4 sb = *reinterpret_cast<const u4*>(xb + row * CHUNK_BYTES + swz(row, 2 * lg + 1));
-      const u4 h = {sa[0], sa[1], sb[0], sb[1]};
-      const u4 l = {sa[2], sa[3], sb[2], sb[3]};
-      bh[j] = __builtin_bit_cast(V, h);
-      bl[j] = __builtin_bit_cast(V, l);
-      lo_or |= (l[0] | l[1]) | (l[2] | l[3]);
-    }
-    const bool do_xlo = __builtin_amdgcn_ballot_w64(lo_or != 0u) != 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int lm = 128 * wn + 16 * i + lr;
-      const V ah = *reinterpret_cast<const V*>(mb + lm * WH_ROW + swz64(lm, lg));
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if constexpr (MODE == MODE_BF16) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-          if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-        } else {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
-          if (do_xlo) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc[i][j], 0, 0, 0);
-        }
-      }
-    }
-  };
-  const float* cl = reinterpret_cast<const float*>(mv.c) + 128 * wn + 4 * lg;
-  const float* wl = reinterpret_cast<const float*>(mv.w) + (int64_t)lr * mv.ldwt + 128 * wn + 4 * lg;
-  auto epilogue = [&](int s) {
-    const float two = 2.0f * mv.postscale;
-    const float* cb = cl + (int64_t)s * WBN;
-    const float* wb = wl + (int64_t)s * WBN;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const f4 c4 = *reinterpret_cast<const f4*>(cb + 16 * i);
-      const f4 w4 = *reinterpret_cast<const f4*>(wb + 16 * i);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        f4 e;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) e[v] = (c4[v] - xn[j]) + two * acc[i][j][v];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) yacc[j] = mfma(w4[v], e[v], yacc[j]);
-        acc[i][j] = f4{0, 0, 0, 0};
-      }
-    }
-  };
-
-  // ---- pipeline: chunk it in buffer it % 3, copies two chunks ahead ----
-  // per chunk: copies of chunk it + 2 issued; split of chunk it (its copies
-  // landed before the previous barrier); barrier; MFMAs; wait for the copies
-  // of chunk it + 1; barrier
-  const int copies = xfast ? kWhCopiesFast : kWhCopiesSlow;
-  issue(0, 0);
-  if (total > 1) {
-    issue(1, 1);
-    if (copies == kWhCopiesFast) __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesFast));
-    else __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesSlow));
-  } else {
-    __builtin_amdgcn_s_waitcnt(kWaitLgkVm(0));
-  }
-  raw_barrier();
-  int b = 0;
-  for (int it = 0; it < total; ++it) {
-    const int s = it / nch, ch = it - (it / nch) * nch;
-    const bool live = (int64_t)s * WBN + 128 * wn < l_pad;
-    const bool ahead = it + 2 < total;
-    if (ahead) issue(it + 2, b == 0 ? 2 : b - 1);
-    split_chunk(b, ch, s == 0);
-    __builtin_amdgcn_s_waitcnt(kWaitLgkVm(15));  // the split's LDS stores
-    raw_barrier();
-    if (live) compute_chunk(b);
-    // chunk it + 1 must have landed; the copies of chunk it + 2 may fly on
-    if (ahead) {
-      if (copies == kWhCopiesFast) __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesFast));
-      else __builtin_amdgcn_s_waitcnt(kWaitLgkVm(kWhCopiesSlow));
-    } else {
-      __builtin_amdgcn_s_waitcnt(kWaitLgkVm(0));
-    }
-    raw_barrier();
-    const bool tile_end = (ch == nch - 1);
-    if (tile_end && s == 0) {
-      // row norms (8 lanes per row, fixed butterfly) through buffer b, which
-      // nothing touches again before the copies issued next iteration
-      float* xnorm = reinterpret_cast<float*>(lds + b * WH_BUF);
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        float t = nacc[u];
-        t += __shfl_xor(t, 4, 64);
-        t += __shfl_xor(t, 2, 64);
-        t += __shfl_xor(t, 1, 64);
-        if (lseg == 0) xnorm[lrow + 64 * u] = t;
-      }
-      __builtin_amdgcn_s_waitcnt(kWaitLgkVm(15));
-      raw_barrier();
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xn[j] = xnorm[64 * wm + 16 * j + lr];
-      __builtin_amdgcn_s_waitcnt(kWaitLgkVm(15));
-      raw_barrier();
-    }
-    if (tile_end && live) epilogue(s);
-    b = (b == 2) ? 0 : b + 1;
-  }
-
-  // ---- add the four landmark quarters in order and store ----
-  __syncthreads();
-  float* ysh = reinterpret_cast<float*>(lds);
-  if (wn > 0) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) ysh[((((wn - 1) * 2 + wm) * 4 + j) * 4 + v) * 64 + lane] = yacc[j][v];
-  }
-  __syncthreads();
-  if (wn == 0) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = 64 * wm + 16 * j + lr;
-      if (row >= nrows) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = 4 * lg + v;
-        float val = yacc[j][v];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) val += ysh[(((q * 2 + wm) * 4 + j) * 4 + v) * 64 + lane];
-        if (col < mv.r) Y[(int64_t)row * ldy + col] = val;
-      }
-    }
-  }
-  __syncthreads();
 }
 
 // ---- split precisions with 32 x 32 x 16 matrix-core products ----
@@ -1614,18 +1229,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(waves_p
   }
 }
 
-// HI: the landmark lo parts are all zero (three-stage form)
-template <int MODE, bool HI>
-__device__ inline void embed_tile_wide_v(const EmbedModelView& mv, const float* __restrict__ X,
-                                         int64_t ldx, int nrows, float* __restrict__ Y, int64_t ldy,
-                                         char* lds) {
-  if constexpr (HI)
-    embed_tile_wide_h<MODE>(mv, X, ldx, nrows, Y, ldy, lds);
-  else
-    embed_tile_wide<MODE>(mv, X, ldx, nrows, Y, ldy, lds);
-}
-
-template <int MODE, bool HI>
+template <int MODE>
 __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_wide(
     EmbedModelView mv, const float* __restrict__ X, int64_t n, int64_t ldx, float* __restrict__ Y,
     int64_t ldy) {
@@ -1634,12 +1238,12 @@ __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row0 = tile * BM;
     const int nrows = (int)((n - row0) < BM ? (n - row0) : BM);
-    embed_tile_wide_v<MODE, HI>(mv, X + row0 * ldx, ldx, nrows, Y + row0 * ldy, ldy, lds);
+    embed_tile_wide<MODE>(mv, X + row0 * ldx, ldx, nrows, Y + row0 * ldy, ldy, lds);
   }
 }
 
-// serving form of the same variants (one tile table entry per 128 rows)
-template <int MODE, bool HI>
+// serving form of the same variant (one tile table entry per 128 rows)
+template <int MODE>
 __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_work_wide(
     const EmbedModelView* __restrict__ views, const TileWork* __restrict__ work,
     const int32_t* __restrict__ nwork) {
@@ -1650,10 +1254,9 @@ __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))
     const EmbedModelView mv = views[tw.model];
     const float* X = reinterpret_cast<const float*>(tw.x) + tw.row0 * tw.ldx;
     float* Y = reinterpret_cast<float*>(tw.y) + tw.row0 * tw.ldy;
-    embed_tile_wide_v<MODE, HI>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+    embed_tile_wide<MODE>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
   }
 }
-
 
 // split precisions: the 32 x 32 variant (one 512-thread block per CU)
 template <int MODE, bool HI>
@@ -1702,12 +1305,12 @@ hipError_t launch_t(const EmbedModelView& mv, const void* X, int64_t n, int64_t 
   return hipGetLastError();
 }
 
-template <int MODE, bool HI>
+template <int MODE>
 hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                          int64_t ldy, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed_wide<MODE, HI>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed_wide<MODE>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, WLDS_BYTES);
     if (e != hipSuccess) return e;
     attr_set = true;
@@ -1717,7 +1320,7 @@ hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int
   // gridDim apart; lane constants are computed (and spilled) once per block
   const int64_t cap = (int64_t)num_cu();
   const int grid = (int)(ntiles < cap ? ntiles : cap);
-  k_embed_wide<MODE, HI><<<grid, WTHREADS, WLDS_BYTES, st>>>(mv, reinterpret_cast<const float*>(X), n,
+  k_embed_wide<MODE><<<grid, WTHREADS, WLDS_BYTES, st>>>(mv, reinterpret_cast<const float*>(X), n,
                                                              ldx, reinterpret_cast<float*>(Y), ldy);
   return hipGetLastError();
 }
@@ -1744,7 +1347,7 @@ template <int MODE>
 hipError_t launch_wide(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                        int64_t ldy, hipStream_t st) {
   if constexpr (MODE == MODE_F32)
-    return launch_wide_v<MODE, false>(mv, X, n, ldx, Y, ldy, st);
+    return launch_wide_v<MODE>(mv, X, n, ldx, Y, ldy, st);
   else
     return mv.m_lo_zero ? launch_s3<MODE, true>(mv, X, n, ldx, Y, ldy, st)
                         : launch_s3<MODE, false>(mv, X, n, ldx, Y, ldy, st);
@@ -1857,7 +1460,7 @@ const void* worklist_fn_rb(int rbc) {
     case 1: return reinterpret_cast<const void*>(&k_embed_work<MODE, 2>);
     case 2: return reinterpret_cast<const void*>(&k_embed_work<MODE, 4>);
     case kWideClass:
-      if constexpr (MODE == MODE_F32) return reinterpret_cast<const void*>(&k_embed_work_wide<MODE, false>);
+      if constexpr (MODE == MODE_F32) return reinterpret_cast<const void*>(&k_embed_work_wide<MODE>);
       else return reinterpret_cast<const void*>(&k_embed_work_s3<MODE, false>);
     default:
       if constexpr (MODE == MODE_F32) return nullptr;
@@ -1883,7 +1486,7 @@ void launch_work_rb(int rbc, int grid, hipStream_t st, const EmbedModelView* v, 
     case 2: k_embed_work<MODE, 4><<<grid, THREADS, LDS_BYTES, st>>>(v, w, nw); break;
     case kWideClass:
       if constexpr (MODE == MODE_F32)
-        k_embed_work_wide<MODE, false><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw);
+        k_embed_work_wide<MODE><<<grid, WTHREADS, WLDS_BYTES, st>>>(v, w, nw);
       else
         k_embed_work_s3<MODE, false><<<grid, S3_THREADS, s3_lds<false>(), st>>>(v, w, nw);
       break;
