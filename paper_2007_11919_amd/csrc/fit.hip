@@ -400,7 +400,8 @@ __global__ __launch_bounds__(1024) void k_set_column(double* __restrict__ V, int
 // (S2, gwork2 its own work space): with both the host can estimate how fast
 // the residual bounds fall.
 
-__global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alpha,
+constexpr int kTriThreads = 256;  // multisection points of the bisection
+__global__ __launch_bounds__(kTriThreads) void k_tridiag(const double* __restrict__ alpha,
                                                  const double* __restrict__ beta,
                                                  const int* __restrict__ ctrl, int k_host, int r,
                                                  double* __restrict__ theta_out,
@@ -429,19 +430,28 @@ __global__ __launch_bounds__(256) void k_tridiag(const double* __restrict__ alph
   const int nr = min(r, k);
   double* al = sm;
   double* be = sm + k;
-  for (int i = t; i < k; i += 256) {
+  for (int i = t; i < k; i += kTriThreads) {
     al[i] = alpha[i];
     be[i] = beta[i];
   }
   __syncthreads();
   double* be2 = sm + 2 * k;
-  double* wk = work_in_lds ? (sm + 3 * k) : gwork;  // [4 arrays][k][nr]
-  tridiag_top<256>(al, be, k, nr, theta, S, ldS, wk, be2);
+  // with work_in_lds, the work arrays ([4][k][nr]) and the vectors (nr x k)
+  // live in LDS, and the vectors are copied out at the end
+  double* wk = work_in_lds ? (sm + 3 * k) : gwork;
+  double* Z = work_in_lds ? (wk + (int64_t)4 * k * nr) : S;
+  const int ldz = work_in_lds ? k : ldS;
+  tridiag_top<kTriThreads>(al, be, k, nr, theta, Z, ldz, wk, be2);
   if (t < nr) {
     const double coupling = fabs(be[k - 1 < 0 ? 0 : k - 1]);
     theta_out[t] = theta[t];
-    bound_out[t] = coupling * fabs(S[(int64_t)t * ldS + (k - 1)]);
+    bound_out[t] = coupling * fabs(Z[(int64_t)t * ldz + (k - 1)]);
   }
+  if (work_in_lds)
+    for (int e = t; e < k * nr; e += kTriThreads) {
+      const int tt = e / k, i = e - tt * k;
+      S[(int64_t)tt * ldS + i] = Z[e];
+    }
   if (probe) return;
   if (t == 0) kout[0] = k;
   if (report) {
@@ -712,11 +722,18 @@ __global__ void k_pack32(const double* __restrict__ M, int64_t ldm, int64_t l_pa
   }
 }
 
-struct DevBuf {
+// The fit's scratch: one block from the library's device-block cache (so
+// repeated fits of one shape reuse it without an allocation), handed back
+// when the fit returns, once the stream has drained.
+struct Scratch {
+  int dev = 0;
+  size_t bytes = 0;
   void* p = nullptr;
   hipStream_t st = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFreeAsync(p, st);
+  ~Scratch() {
+    if (!p) return;
+    (void)hipStreamSynchronize(st);
+    model_release(dev, bytes, p);
   }
 };
 
@@ -730,7 +747,7 @@ struct DevBuf {
 
 namespace {
 
-constexpr size_t kTriLdsMax = 150 * 1024;
+constexpr size_t kTriLdsMax = 144 * 1024;  // beside about 13 KB of static LDS
 
 // Ritz solve of the k x k tridiagonal matrix; its work arrays live in LDS
 // when they fit.
@@ -748,10 +765,10 @@ hipError_t launch_tridiag(const double* alpha, const double* beta, const int* ct
   }
   const int nr = std::min(r, k_host);
   const size_t base = sizeof(double) * 3 * (size_t)k_host;
-  const size_t work = sizeof(double) * 4 * (size_t)k_host * nr;
+  const size_t work = sizeof(double) * 5 * (size_t)k_host * nr;  // work arrays and vectors
   const int in_lds = (base + work <= kTriLdsMax) ? 1 : 0;
   const unsigned grid = (d_probe > 0) ? 2u : 1u;
-  k_tridiag<<<grid, 256, base + (in_lds ? work : 0), st>>>(alpha, beta, ctrl, k_host, r, theta, bound, S,
+  k_tridiag<<<grid, kTriThreads, base + (in_lds ? work : 0), st>>>(alpha, beta, ctrl, k_host, r, theta, bound, S,
                                                           ldS, gwork, kout, in_lds, report, qn, d_probe,
                                                           theta2, bound2, S2, gwork2);
   return hipGetLastError();
@@ -828,21 +845,31 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   MDS_HIP(hipMemsetAsync(m.base, 0, lay.off, st));
 
   // ---- scratch (stream-ordered, freed when the fit returns) ----
-  DevBuf bDQ, bV, bsmall, bS, bwork, bVr, bab;
-  MDS_HIP(hipMallocAsync(&bDQ.p, sizeof(double) * l * l, st));
-  bDQ.st = st;
-  MDS_HIP(hipMallocAsync(&bV.p, sizeof(double) * l * (kcap + 1), st));
-  bV.st = st;
-  MDS_HIP(hipMallocAsync(&bsmall.p, sizeof(double) * ((size_t)l * 7 + 64), st));
-  bsmall.st = st;
-  MDS_HIP(hipMallocAsync(&bS.p, sizeof(double) * (size_t)(kcap + 1) * (2 * r + 1), st));
-  bS.st = st;
-  MDS_HIP(hipMallocAsync(&bwork.p, sizeof(double) * (size_t)(kcap + 1) * 4 * (2 * r + 1), st));
-  bwork.st = st;
-  MDS_HIP(hipMallocAsync(&bVr.p, sizeof(double) * l * r, st));
-  bVr.st = st;
-  MDS_HIP(hipMallocAsync(&bab.p, sizeof(double) * ((size_t)2 * (kcap + 1) + 6 * MDS_MAX_R + 32), st));
-  bab.st = st;
+  // affine-map partials: landmark chunks (each wave walks a few landmarks,
+  // so the loop is not a chain of memory latencies), up to 64, within 64 MB
+  const int64_t aff_cols = (int64_t)r * (p + 1);
+  const int aff_nz = (int)std::max<int64_t>(1, std::min<int64_t>({64, (l + 15) / 16,
+                                                                   (int64_t)(8 << 20) / aff_cols}));
+  Layout sl;
+  const size_t sDQ = sl.take(sizeof(double) * l * l);
+  const size_t sV = sl.take(sizeof(double) * l * (kcap + 1));
+  const size_t ssmall = sl.take(sizeof(double) * ((size_t)l * 7 + 64));
+  const size_t sS = sl.take(sizeof(double) * (size_t)(kcap + 1) * (2 * r + 1));
+  const size_t swork = sl.take(sizeof(double) * (size_t)(kcap + 1) * 4 * (2 * r + 1));
+  const size_t sVr = sl.take(sizeof(double) * l * r);
+  const size_t sab = sl.take(sizeof(double) * ((size_t)2 * (kcap + 1) + 6 * MDS_MAX_R + 32));
+  const size_t saff = sl.take(vectors ? sizeof(double) * (size_t)aff_nz * aff_cols : 0);
+  Scratch scr;
+  scr.dev = m.dev;
+  scr.bytes = sl.off;
+  scr.st = st;
+  scr.p = model_alloc(m.dev, sl.off);
+  if (!scr.p) return set_error(MDS_ERR_OOM, "device allocation of the fit scratch failed");
+  char* sb = static_cast<char*>(scr.p);
+  struct {
+    void* p;
+  } bDQ{sb + sDQ}, bV{sb + sV}, bsmall{sb + ssmall}, bS{sb + sS}, bwork{sb + swork}, bVr{sb + sVr},
+      bab{sb + sab}, baff{sb + saff};
   double* DQ = (double*)bDQ.p;
   double* Vk = (double*)bV.p;
   double* d1 = (double*)bsmall.p;
@@ -1072,20 +1099,11 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     k_pack32<<<grid, 256, 0, st>>>((const double*)m.m64, ldm, l_pad, p, nch32, (float*)m.m32,
                                    (uint16_t*)m.mbf, (uint16_t*)m.mh, (uint16_t*)m.sbf, (uint16_t*)m.sh,
                                    m.l_split, scales, ctrl + 10);
-    // landmark chunks for the affine map (each wave walks a few landmarks,
-    // so the loop is not a chain of memory latencies): up to 64, partials
-    // within 64 MB
-    const int64_t cols = (int64_t)r * (p + 1);
-    const int nz = (int)std::max<int64_t>(1, std::min<int64_t>({64, (l + 15) / 16,
-                                                                (int64_t)(8 << 20) / cols}));
-    DevBuf baff;
-    MDS_HIP(hipMallocAsync(&baff.p, sizeof(double) * (size_t)nz * cols, st));
-    baff.st = st;
-    dim3 agrid((unsigned)((p + 1 + 63) / 64), (unsigned)nz);
+    dim3 agrid((unsigned)((p + 1 + 63) / 64), (unsigned)aff_nz);
     k_affine_map<<<agrid, 256, 0, st>>>((const double*)m.m64, ldm, l, p, (const double*)m.w64, ldw,
                                         (const double*)m.c64, r, (double*)baff.p);
-    k_affine_sum<<<(unsigned)((cols + 255) / 256), 256, 0, st>>>(
-        (const double*)baff.p, nz, p, r, (double*)m.aff64, (float*)m.aff32, (double*)m.affb64,
+    k_affine_sum<<<(unsigned)((aff_cols + 255) / 256), 256, 0, st>>>(
+        (const double*)baff.p, aff_nz, p, r, (double*)m.aff64, (float*)m.aff32, (double*)m.affb64,
         (float*)m.affb32);
   } else {
     k_scale<<<1, 256, 0, st>>>(rowmax, 0, scales);  // unused without vectors

@@ -94,40 +94,29 @@ __device__ __forceinline__ void inverse_sweep(const double* __restrict__ al,
   double zc = z[0];
   double cur_d = al[0] - th;
   double cur_u = (k > 1) ? be[0] : 0.0;
-  double cur_u2 = 0.0;
   for (int i = 0; i < k - 1; ++i) {
+    // rows i (cur_d, cur_u, 0 | zc) and i + 1 (sub, nd, nu | zn): the row
+    // with the larger entry in column i is the pivot row, the other one is
+    // eliminated with it (selects, so the lanes of a wave do not diverge)
     const double sub = be[i];
     const double nd = al[i + 1] - th;
     const double nu = (i + 1 < k - 1) ? be[i + 1] : 0.0;
     const double zn = z[i + 1];
-    double di, u1, u2, y;
-    if (fabs(cur_d) >= fabs(sub)) {
-      di = (fabs(cur_d) < pert) ? (cur_d < 0 ? -pert : pert) : cur_d;
-      const double mlt = sub * rcp_refined(di);
-      u1 = cur_u;
-      u2 = cur_u2;
-      y = zc;
-      zc = zn - mlt * zc;
-      cur_d = nd - mlt * cur_u;
-      cur_u = nu - mlt * cur_u2;
-    } else {
-      const double mlt = cur_d / sub;  // |sub| > |cur_d|; sub may be tiny
-      di = sub;
-      u1 = nd;
-      u2 = nu;
-      y = zn;
-      zc = zc - mlt * zn;
-      const double nd2 = cur_u - mlt * nd;
-      const double nu2 = cur_u2 - mlt * nu;
-      cur_d = nd2;
-      cur_u = nu2;
-    }
-    cur_u2 = 0.0;
+    const bool swap = fabs(cur_d) < fabs(sub);
+    const double pd = swap ? sub : cur_d;
+    const double p1 = swap ? nd : cur_u, p2 = swap ? nu : 0.0, pz = swap ? zn : zc;
+    const double od = swap ? cur_d : sub;
+    const double o1 = swap ? cur_u : nd, o2 = swap ? 0.0 : nu, oz = swap ? zc : zn;
+    const double rp = rcp_refined((fabs(pd) < pert) ? (pd < 0 ? -pert : pert) : pd);
+    const double mlt = od * rp;
+    cur_d = fma(-mlt, p1, o1);
+    cur_u = fma(-mlt, p2, o2);
+    zc = fma(-mlt, pz, oz);
     double* w = wk + (int64_t)i * 4 * nr;
-    w[0] = rcp_refined((fabs(di) < pert) ? (di < 0 ? -pert : pert) : di);
-    w[nr] = u1;
-    w[2 * nr] = u2;
-    w[3 * nr] = y;
+    w[0] = rp;
+    w[nr] = p1;
+    w[2 * nr] = p2;
+    w[3 * nr] = pz;
   }
   double dl = (fabs(cur_d) < pert) ? (cur_d < 0 ? -pert : pert) : cur_d;
   // backward substitution with a rolling window of two values
