@@ -106,7 +106,9 @@ def embed_kernel(prec, p, l, r):
     span = -(-l_pad // 512) * 512
     fills = l_pad >= 512 and 4 * (span - l_pad) < span
     if r <= 16 and (fills or (prec != "fp32" and p >= 256)):
-        return f"k_embed_wide<{prec.upper()}> (512 landmarks per pass over a row tile)"
+        if prec == "fp32":
+            return "k_embed_wide<FP32> (512 landmarks per pass over a row tile)"
+        return f"k_embed_s3<{prec.upper()}> (32 x 32 x 16 split products, 512 landmarks per pass)"
     return f"k_embed<{prec.upper()}> (128 landmarks per pass over a row tile)"
 
 
