@@ -840,10 +840,15 @@ def main():
         model = mds.fit_landmarks(Xd, w["l"], w["r"], seed=0)
         if args.only_embed:
             Y = mds.embed(model, Xd, prec=args.only_embed)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             for _ in range(args.iters):
                 mds.embed(model, Xd, prec=args.only_embed, Y=Y)
+            e1.record()
             torch.cuda.synchronize()
-            print(json.dumps({"only_embed": args.only_embed, "iters": args.iters}))
+            print(json.dumps({"only_embed": args.only_embed, "iters": args.iters,
+                              "ms_per_launch": e0.elapsed_time(e1) / max(1, args.iters)}))
             return
         if args.only_affine:
             Y = mds.embed_affine(model, Xd, prec="fp32")

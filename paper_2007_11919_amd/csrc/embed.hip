@@ -821,9 +821,24 @@ __device__ inline f16v mfma32(const h8& a, const h8& b, f16v c) {
 // byte offset of 16-byte segment g (0..3) of row `row` in a plane of 64-byte rows
 __device__ inline int s3_off(int row, int g) { return row * 64 + ((g ^ ((row >> 2) & 3)) << 4); }
 
-template <int MODE, bool HI>
+// Data part of a buffer: 8 regions of 16 rows, each a 1 KB hi plane then a
+// 1 KB lo plane; the 16 bytes holding values 8 g .. 8 g + 7 of row `row`
+// sit in slot 4 (row & 15) + (g ^ ((row >> 1) & 3)) of its region's plane.
+// Slot L of a region belongs to lane L of wave `region`, which is how a
+// direct copy into LDS lays out 64 lanes x 16 bytes.
+constexpr int S3_XLO = 1024;  // lo plane after the hi plane of a region
+__device__ inline int s3_xoff(int row, int g) {
+  return (row >> 4) * 2048 + ((((row & 15) << 2) + (g ^ ((row >> 1) & 3))) << 4);
+}
+
+// XDMA (landmarks without lo parts, 16-byte aligned rows, p a multiple of 4):
+// the data chunks are copied straight into LDS as well, and each thread
+// splits its own 32 bytes there in place, so every memory operation of the
+// chunk loop is a copy into LDS and the waits count them exactly.
+template <int MODE, bool HI, bool XDMA>
 __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict__ X, int64_t ldx,
                               int nrows, float* __restrict__ Y, int64_t ldy, char* lds) {
+  static_assert(!XDMA || HI, "direct data copies need the third buffer");
   using V = typename std::conditional<MODE == MODE_BF16, bf8, h8>::type;
   constexpr int NBUF = s3_nbuf<HI>();
   constexpr int BUF = s3_buf<HI>();
@@ -859,14 +874,16 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
   float nacc = 0.f;
   float xn[2] = {0.f, 0.f};
 
-  // data: thread owns values 8 q8 .. 8 q8 + 7 of row xrow of each chunk;
-  // byte offsets inside the tile are 32-bit, chunk offsets uniform
+  // data: thread owns values 8 gx .. 8 gx + 7 of row xrow of each chunk, gx
+  // chosen so that its hi and lo parts sit in slot `lane` of its wave's
+  // region; byte offsets inside the tile are 32-bit, chunk offsets uniform
   const int xrow = tid >> 2;
   const int q8 = tid & 3;
+  const int gx = q8 ^ ((xrow >> 1) & 3);
   const char* xbase = reinterpret_cast<const char*>(X);
   const uint32_t xrow_off = (uint32_t)((int64_t)(xrow < nrows ? xrow : nrows - 1) * ldx * 4);
-  const uint32_t xoff = xrow_off + 32u * (uint32_t)q8;
-  const int sw_off = s3_off(xrow, q8);  // the thread's 16 bytes in a data plane
+  const uint32_t xoff = xrow_off + 32u * (uint32_t)gx;
+  const int sw_off = s3_xoff(xrow, gx);  // = 2048 wave + 16 lane
   f4 xa[2], xb[2];                     // 8 values of two chunks in flight
   auto load_x = [&](int ch, auto slot_tag) {
     constexpr int SL = decltype(slot_tag)::value;
@@ -881,12 +898,12 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
         // last chunk: rows past nrows repeat the last row; a 16-byte piece
         // past p (p is a multiple of 4) re-reads the row's first values
         // instead (finite, zeroed by the split), so no read leaves the row
-        const int k = 32 * ch + 8 * q8;
+        const int k = 32 * ch + 8 * gx;
         xa_ = *reinterpret_cast<const f4*>(xbase + (k < p ? (int64_t)ch * 128 + xoff : xrow_off));
         xb_ = *reinterpret_cast<const f4*>(xbase + (k + 4 < p ? (int64_t)ch * 128 + xoff + 16 : xrow_off));
       }
     } else {
-      const int k = 32 * ch + 8 * q8;
+      const int k = 32 * ch + 8 * gx;
       Seg<float, 4> v0, v1;
       if (xrow < nrows) {
         v0 = load_seg<float, 4>(X + (int64_t)xrow * ldx, k, p, xvec);
@@ -902,18 +919,11 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
       }
     }
   };
-  // split of chunk ch's registers into buffer b; returns whether a data lo
-  // part is nonzero
-  auto split = [&](int ch, int b, bool norms, auto slot_tag) -> bool {
-    constexpr int SL = decltype(slot_tag)::value;
-    float x[8];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      x[e] = xa[SL][e];
-      x[4 + e] = xb[SL][e];
-    }
+  // split of chunk ch's 8 values (x) into buffer b; returns whether a data
+  // lo part is nonzero
+  auto split_vals = [&](float (&x)[8], int ch, int b, bool norms) -> bool {
     if (32 * ch + 32 > p) {
-      const int k0 = 32 * ch + 8 * q8;
+      const int k0 = 32 * ch + 8 * gx;
 #pragma unroll
       for (int e = 0; e < 8; ++e) x[e] = (k0 + e < p) ? x[e] : 0.f;
     }
@@ -947,8 +957,45 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
     }
     char* xh = lds + b * BUF + sw_off;
     *reinterpret_cast<u4*>(xh) = u4{hi[0], hi[1], hi[2], hi[3]};
-    *reinterpret_cast<u4*>(xh + S3_XP) = u4{lo[0], lo[1], lo[2], lo[3]};
+    *reinterpret_cast<u4*>(xh + S3_XLO) = u4{lo[0], lo[1], lo[2], lo[3]};
     return ((lo[0] | lo[1]) | (lo[2] | lo[3])) != 0u;
+  };
+  // from the register slot the values were loaded into
+  auto split = [&](int ch, int b, bool norms, auto slot_tag) -> bool {
+    constexpr int SL = decltype(slot_tag)::value;
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x[e] = xa[SL][e];
+      x[4 + e] = xb[SL][e];
+    }
+    return split_vals(x, ch, b, norms);
+  };
+  // in place, from the thread's own two copied 16-byte pieces in buffer b
+  auto split_lds = [&](int ch, int b, bool norms) -> bool {
+    const char* xh = lds + b * BUF + sw_off;
+    const f4 va = *reinterpret_cast<const f4*>(xh);
+    const f4 vb = *reinterpret_cast<const f4*>(xh + S3_XLO);
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x[e] = va[e];
+      x[4 + e] = vb[e];
+    }
+    return split_vals(x, ch, b, norms);
+  };
+  // data copies of chunk ch into buffer b: lane L copies the 16-byte pieces
+  // u = 0, 1 of its values (raw FP32) into slot L of its region's planes u;
+  // a piece past p re-reads the row's first values (zeroed by the split)
+  auto dma_x = [&](int ch, int b) {
+    char* xb_ = lds + b * BUF + wave * 2048;
+    const int k = 32 * ch + 8 * gx;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const char* src = xbase + (k + 4 * u < p ? (int64_t)ch * 128 + xoff + 16 * u : (int64_t)xrow_off);
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                       (__attribute__((address_space(3))) void*)(xb_ + u * S3_XLO), 16, 0, 0);
+    }
   };
   // landmark copies of chunk (s, ch) into buffer b: wave w copies bytes
   // [4096 w, 4096 w + 4096) of each part
@@ -971,9 +1018,10 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
     }
   };
 
-  // operand offsets: row block j and landmark block i add 2048 bytes (32
-  // rows of 64 bytes; the swizzle depends on row bits 2..3 only)
-  const int bo0 = s3_off(64 * wm + l31, half), bo1 = s3_off(64 * wm + l31, 2 + half);
+  // operand offsets: data row block j adds 4096 bytes (two regions) and
+  // landmark block i 2048 (32 rows of 64 bytes); the swizzles depend on row
+  // bits 1..3 only
+  const int bo0 = s3_xoff(64 * wm + l31, half), bo1 = s3_xoff(64 * wm + l31, 2 + half);
   const int ao0 = s3_off(128 * wn + l31, half), ao1 = s3_off(128 * wn + l31, 2 + half);
   // products of the chunk in buffer b: first those with the data hi parts
   // (hi.hi, then lo.hi when the landmarks have lo parts) for both k-steps,
@@ -988,7 +1036,7 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
         const char* pa = base + 2 * S3_XP + (ks ? ao1 : ao0);
         V bx[2], ah[4], al[4];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bx[j] = *reinterpret_cast<const V*>(pb + 2048 * j);
+        for (int j = 0; j < 2; ++j) bx[j] = *reinterpret_cast<const V*>(pb + 4096 * j);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           ah[i] = *reinterpret_cast<const V*>(pa + 2048 * i);
@@ -1007,7 +1055,7 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
       }
     };
     pass(0, true);
-    if (do_xlo) pass(S3_XP, MODE == MODE_BF16);
+    if (do_xlo) pass(S3_XLO, MODE == MODE_BF16);
   };
 
   // e = c - |x|^2 + 2 s and Y^T += W^T E^T for the wave's landmarks of pass
@@ -1059,10 +1107,11 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
   // ---- pipeline ----
   // iteration it (pass s, chunk ch): landmark copies of chunk it + MAHEAD
   // (into the buffer the products of chunk it - 1 read), then data loads of
-  // chunk it + 2 into the register slot chunk it used; products of chunk
-  // it; split of chunk it + 1 (loaded two iterations back) into its buffer;
-  // wait for the landmark copies of chunk it + 1; one barrier.  The loop is
-  // unrolled by two so that the register slots are fixed.
+  // chunk it + 2 into the register slot chunk it used (XDMA: data copies of
+  // chunk it + 2 into its buffer); products of chunk it; split of chunk
+  // it + 1 (loaded two iterations back) into its buffer; wait for the
+  // landmark copies of chunk it + 1; one barrier.  The loop is unrolled by
+  // two so that the register slots are fixed.
   using S0 = std::integral_constant<int, 0>;
   using S1 = std::integral_constant<int, 1>;
   const int cm = HI ? 4 : 8;  // landmark copies per chunk and wave
@@ -1076,10 +1125,20 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
       }
     }
   }
-  load_x(0, S0{});
-  if (total > 1) load_x(1 % nch, S1{});
+  bool nz0;
+  if constexpr (XDMA) {
+    dma_x(0, 0);
+    if (total > 1) dma_x(1 % nch, 1);
+    __builtin_amdgcn_s_waitcnt(wait_imm(0, 15));
+    __builtin_amdgcn_sched_barrier(0);
+    nz0 = split_lds(0, 0, true);
+  } else {
+    load_x(0, S0{});
+    if (total > 1) load_x(1 % nch, S1{});
+    nz0 = split(0, 0, true, S0{});
+  }
   {
-    const bool nz = split(0, 0, true, S0{});
+    const bool nz = nz0;
     if constexpr (HI) {
       const bool any = __builtin_amdgcn_ballot_w64(nz) != 0;
       if (lane == 0) flags[wave] = any ? 1 : 0;
@@ -1093,14 +1152,23 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
   int ns = (nch == 1) ? 1 : 0, nc = (nch == 1) ? 0 : 1;
   int ms = MAHEAD / nch, mc = MAHEAD % nch;
   int lc = 2 % nch;
-  auto step = [&](int it, auto cur) {
+  // FULL (direct data copies only): a step with it + 2 < total, whose
+  // copies are issued without a condition, so that the copies in flight
+  // are the same on every path and the waits count them exactly
+  auto step = [&](int it, auto cur, auto full) {
     using SC = decltype(cur);
     using SN = std::integral_constant<int, 1 - SC::value>;
+    constexpr bool FULL = decltype(full)::value;
     const bool live = (int64_t)s * WBN + 128 * wn < l_pad;
-    const bool next = it + 1 < total;
+    const bool next = FULL || it + 1 < total;
     const int bn = (b + 1 == NBUF) ? 0 : b + 1;
-    if (it + MAHEAD < total) dma_m(ms, mc, (b + MAHEAD) % NBUF);
-    if (it + 2 < total) load_x(lc, SC{});
+    if (FULL || it + MAHEAD < total) dma_m(ms, mc, (b + MAHEAD) % NBUF);
+    if (FULL || it + 2 < total) {
+      if constexpr (XDMA)
+        dma_x(lc, (b + 2) % NBUF);
+      else
+        load_x(lc, SC{});
+    }
     bool do_xlo = true;
     if constexpr (HI) {
       const int* fb = flags + b * 8;
@@ -1108,18 +1176,30 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
     }
     if (live) compute(b, do_xlo);
     if (next) {
-      const bool nz = split(nc, bn, ns == 0, SN{});
+      bool nz;
+      if constexpr (XDMA) {
+        // the data copies of chunk it + 1 (one step back) have landed once
+        // at most this step's copies remain
+        if (FULL || it + 2 < total)
+          __builtin_amdgcn_s_waitcnt(wait_imm(cm + 2, 15));
+        else
+          __builtin_amdgcn_s_waitcnt(wait_imm(0, 15));
+        __builtin_amdgcn_sched_barrier(0);
+        nz = split_lds(nc, bn, ns == 0);
+      } else {
+        nz = split(nc, bn, ns == 0, SN{});
+      }
       if constexpr (HI) {
         const bool any = __builtin_amdgcn_ballot_w64(nz) != 0;
         if (lane == 0) flags[bn * 8 + wave] = any ? 1 : 0;
       }
     }
     // the landmark copies of chunk it + 1 have landed once at most the
-    // later memory operations remain: (three buffers) data loads of chunks
-    // it + 1 and it + 2 and copies of chunk it + 2, (two buffers) data
-    // loads of chunk it + 2; the split's stores are done
-    if (HI && it + 2 < total) __builtin_amdgcn_s_waitcnt(wait_imm(cm + 4, 0));
-    else if (!HI && it + 2 < total) __builtin_amdgcn_s_waitcnt(wait_imm(2, 0));
+    // later memory operations remain: (three buffers) data loads or copies
+    // of chunks it + 1 and it + 2 and landmark copies of chunk it + 2, (two
+    // buffers) data loads of chunk it + 2; the split's stores are done
+    if (HI && (FULL || it + 2 < total)) __builtin_amdgcn_s_waitcnt(wait_imm(cm + 4, 0));
+    else if (!HI && (FULL || it + 2 < total)) __builtin_amdgcn_s_waitcnt(wait_imm(2, 0));
     else __builtin_amdgcn_s_waitcnt(wait_imm(0, 0));
     raw_barrier();
     if (ch == nch - 1) {
@@ -1154,9 +1234,18 @@ __device__ void embed_tile_s3(const EmbedModelView& mv, const float* __restrict_
     }
     if (++lc == nch) lc = 0;
   };
-  for (int it = 0; it < total; it += 2) {
-    step(it, S0{});
-    if (it + 1 < total) step(it + 1, S1{});
+  using FullStep = std::true_type;
+  using TailStep = std::false_type;
+  int it = 0;
+  if constexpr (XDMA) {
+    for (; it + 3 < total; it += 2) {
+      step(it, S0{}, FullStep{});
+      step(it + 1, S1{}, FullStep{});
+    }
+  }
+  for (; it < total; it += 2) {
+    step(it, S0{}, TailStep{});
+    if (it + 1 < total) step(it + 1, S1{}, TailStep{});
   }
 
   // ---- add the four landmark quarters in order and store ----
@@ -1259,7 +1348,7 @@ __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))
 }
 
 // split precisions: the 32 x 32 variant (one 512-thread block per CU)
-template <int MODE, bool HI>
+template <int MODE, bool HI, bool XDMA>
 __global__ __launch_bounds__(S3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_s3(
     EmbedModelView mv, const float* __restrict__ X, int64_t n, int64_t ldx, float* __restrict__ Y,
     int64_t ldy) {
@@ -1268,7 +1357,7 @@ __global__ __launch_bounds__(S3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row0 = tile * BM;
     const int nrows = (int)((n - row0) < BM ? (n - row0) : BM);
-    embed_tile_s3<MODE, HI>(mv, X + row0 * ldx, ldx, nrows, Y + row0 * ldy, ldy, lds);
+    embed_tile_s3<MODE, HI, XDMA>(mv, X + row0 * ldx, ldx, nrows, Y + row0 * ldy, ldy, lds);
   }
 }
 
@@ -1283,7 +1372,8 @@ __global__ __launch_bounds__(S3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     const EmbedModelView mv = views[tw.model];
     const float* X = reinterpret_cast<const float*>(tw.x) + tw.row0 * tw.ldx;
     float* Y = reinterpret_cast<float*>(tw.y) + tw.row0 * tw.ldy;
-    embed_tile_s3<MODE, HI>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+    // the register path for every request (the same arithmetic, bit for bit)
+    embed_tile_s3<MODE, HI, false>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
   }
 }
 
@@ -1325,12 +1415,12 @@ hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int
   return hipGetLastError();
 }
 
-template <int MODE, bool HI>
+template <int MODE, bool HI, bool XDMA>
 hipError_t launch_s3(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                      int64_t ldy, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed_s3<MODE, HI>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed_s3<MODE, HI, XDMA>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, s3_lds<HI>());
     if (e != hipSuccess) return e;
     attr_set = true;
@@ -1338,8 +1428,8 @@ hipError_t launch_s3(const EmbedModelView& mv, const void* X, int64_t n, int64_t
   const int64_t ntiles = (n + BM - 1) / BM;
   const int64_t cap = (int64_t)num_cu();
   const int grid = (int)(ntiles < cap ? ntiles : cap);
-  k_embed_s3<MODE, HI><<<grid, S3_THREADS, s3_lds<HI>(), st>>>(mv, reinterpret_cast<const float*>(X), n, ldx,
-                                                                reinterpret_cast<float*>(Y), ldy);
+  k_embed_s3<MODE, HI, XDMA><<<grid, S3_THREADS, s3_lds<HI>(), st>>>(
+      mv, reinterpret_cast<const float*>(X), n, ldx, reinterpret_cast<float*>(Y), ldy);
   return hipGetLastError();
 }
 
@@ -1349,8 +1439,15 @@ hipError_t launch_wide(const EmbedModelView& mv, const void* X, int64_t n, int64
   if constexpr (MODE == MODE_F32)
     return launch_wide_v<MODE>(mv, X, n, ldx, Y, ldy, st);
   else
-    return mv.m_lo_zero ? launch_s3<MODE, true>(mv, X, n, ldx, Y, ldy, st)
-                        : launch_s3<MODE, false>(mv, X, n, ldx, Y, ldy, st);
+  {
+    // data copies straight into LDS need 16-byte aligned rows and p a
+    // multiple of 4 (whole 16-byte pieces), and the third buffer
+    const bool xdma = mv.m_lo_zero && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                      ((ldx * (int64_t)sizeof(float)) % 16 == 0) && (mv.p % 4 == 0);
+    if (xdma) return launch_s3<MODE, true, true>(mv, X, n, ldx, Y, ldy, st);
+    return mv.m_lo_zero ? launch_s3<MODE, true, false>(mv, X, n, ldx, Y, ldy, st)
+                        : launch_s3<MODE, false, false>(mv, X, n, ldx, Y, ldy, st);
+  }
 }
 
 template <int MODE, typename TX>
