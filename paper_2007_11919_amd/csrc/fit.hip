@@ -61,12 +61,22 @@ __global__ void k_gather(const TX* __restrict__ X, int64_t ldx, const int64_t* _
 
 // ------------------------------------------------ landmark squared distances
 // 64x64 output tile per block, 4x4 per thread, contraction staged by 16.
+// Blocks take the tiles on and above the diagonal (linear index t -> tile
+// row bi <= tile column bj) and also write the mirrored tile: each entry is
+// a sum of (a_k - b_k)^2 over k in order, which is the same number with a
+// and b exchanged, so Delta1 comes out exactly symmetric.
 __global__ __launch_bounds__(256) void k_sqdist(const double* __restrict__ M, int64_t ldm,
                                                 int64_t l, int64_t p, double* __restrict__ D) {
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
+  __shared__ double Tt[64][65];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  const int tl = (int)blockIdx.x;
+  int bj = (int)((sqrt(8.0 * tl + 1.0) - 1.0) * 0.5);
+  while ((bj + 1) * (bj + 2) / 2 <= tl) ++bj;
+  while (bj * (bj + 1) / 2 > tl) --bj;
+  const int bi = tl - bj * (bj + 1) / 2;
+  const int64_t i0 = (int64_t)bi * 64, j0 = (int64_t)bj * 64;
   double acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -108,6 +118,18 @@ __global__ __launch_bounds__(256) void k_sqdist(const double* __restrict__ M, in
       const int64_t i = i0 + ty * 4 + x, j = j0 + tx * 4 + y;
       if (i < l && j < l) D[i * l + j] = acc[x][y];
     }
+  if (bi == bj) return;
+  // the mirrored tile, transposed through LDS so that the writes are rows
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) Tt[tx * 4 + y][ty * 4 + x] = acc[x][y];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int jl = e >> 6, il = e & 63;
+    const int64_t j = j0 + jl, i = i0 + il;
+    if (i < l && j < l) D[j * l + i] = Tt[jl][il];
+  }
 }
 
 // Copy a caller's squared-dissimilarity matrix into Delta1, flagging
@@ -914,8 +936,8 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
       k_gather<double><<<grid, 256, 0, st>>>((const double*)X, ldx, idx_dev, l, p, ldm,
                                              (double*)m.m64, ctrl + 3);
     LAUNCH_CHECK("gather");
-    dim3 sq_grid((unsigned)((l + 63) / 64), (unsigned)((l + 63) / 64));
-    k_sqdist<<<sq_grid, 256, 0, st>>>((const double*)m.m64, ldm, l, p, DQ);
+    const int64_t sq_tiles = (l + 63) / 64;
+    k_sqdist<<<(unsigned)(sq_tiles * (sq_tiles + 1) / 2), 256, 0, st>>>((const double*)m.m64, ldm, l, p, DQ);
     LAUNCH_CHECK("sqdist");
   }
   k_rowmean<<<(unsigned)l, 256, 0, st>>>(DQ, l, d1);
