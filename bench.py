@@ -850,10 +850,14 @@ def main():
             print(json.dumps({"only_embed": args.only_embed, "iters": args.iters,
                               "ms_per_launch": e0.elapsed_time(e1) / max(1, args.iters)}))
             return
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         if args.only_affine:
             Y = mds.embed_affine(model, Xd, prec="fp32")
+            torch.cuda.synchronize()
+            e0.record()
             for _ in range(args.iters):
                 mds.embed_affine(model, Xd, prec="fp32", Y=Y)
+            e1.record()
         else:
             idx = torch.from_numpy(model.landmarks()).to(dev)
             M = Xd[idx]
@@ -864,10 +868,14 @@ def main():
                 A2[s0:s0 + 100_000] = ((xb * xb).sum(1, keepdim=True) + mn[None, :]
                                        - 2.0 * (xb @ M.T)).clamp_min_(0)
             Y = mds.embed_from_sqdist(model, A2, prec="fp32")
+            torch.cuda.synchronize()
+            e0.record()
             for _ in range(args.iters):
                 mds.embed_from_sqdist(model, A2, prec="fp32", Y=Y)
+            e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"only": "affine" if args.only_affine else "sqdist", "iters": args.iters}))
+        print(json.dumps({"only": "affine" if args.only_affine else "sqdist", "iters": args.iters,
+                          "ms_per_launch": e0.elapsed_time(e1) / max(1, args.iters)}))
         return
 
     cpu = not args.no_cpu_baseline

@@ -71,6 +71,32 @@ def test_batch_invariance_bitwise():
         assert np.array_equal(part, full[s:s + k])
 
 
+
+@pytest.mark.parametrize("p,r", [(132, 33), (8, 7), (124, 64)])
+def test_fp32_row_stream(p, r):
+    """FP32 shapes around the kernel's 32-column steps (p = 132 ends in a
+    step of 4 columns, p = 124 in one of 28, p = 8 is a single partial
+    step) and up to four 16-column output tiles (r = 64).  Rows that
+    start on 16-byte boundaries take the unmasked 16-byte loads; the same
+    rows at an odd row stride take the masked loads.  Both match the
+    oracle, and each other to FP32 rounding."""
+    n, l = 3000, 300
+    X = gen.gaussian_columns(n, np.linspace(6.0, 1.0, p), seed=p, dtype=np.float32)
+    model = mds().fit_landmarks(dev(X), l, r, seed=4)
+    fit = om.fit_landmarks(X, l, r, seed=4)
+    Yo = om.interpolate_affine(fit, X)
+    Y = mds().embed_affine(model, dev(X), prec="fp32").cpu().numpy()
+    e = errors.column_errors(Y, Yo)
+    assert e["rms_rel"] <= TOL["fp32"] and e["maxabs_rms"] <= TOL["fp32"], e
+    wide = np.zeros((n, p + 1), np.float32)
+    wide[:, :p] = X
+    Ys = mds().embed_affine(model, dev(wide)[:, :p], prec="fp32").cpu().numpy()
+    es = errors.column_errors(Ys, Yo)
+    assert es["rms_rel"] <= TOL["fp32"] and es["maxabs_rms"] <= TOL["fp32"], es
+    assert errors.column_errors(Ys, Y)["maxabs_rms"] <= 1e-5
+    model.free()
+
+
 def test_error_codes():
     m = mds()
     X = gen.small_gaussian(300, seed=17)

@@ -81,6 +81,31 @@ def test_ragged_and_strided(n):
     check(mds().embed_from_sqdist(model, Ad.float(), prec="fp32").cpu().numpy(), Yo, "fp32")
 
 
+
+@pytest.mark.parametrize("l,r", [(132, 12), (124, 5), (400, 3)])
+def test_fp32_row_stream(l, r):
+    """FP32 shapes around the kernel's 64-landmark chunks (l = 132 ends
+    in a chunk of 4, l = 124 in one of 60, l = 400 in one of
+    16).  Rows of A2 that start on 16-byte boundaries take the 16-byte
+    loads; the same rows at an odd row stride take the element loads.
+    Both match the oracle, and each other to FP32 rounding."""
+    X = gen.small_gaussian(2000, seed=9)
+    D = l1_sqdist(X[:l], X[:l])
+    model = mds().fit_from_sqdist(dev(D), r)
+    fit = oracle.fit_from_sqdist(D, r)
+    A2 = l1_sqdist(X[l:], X[:l])
+    Yo = oracle.interpolate_sqdist(fit, A2)
+    A = A2.astype(np.float32)
+    Y = mds().embed_from_sqdist(model, dev(A), prec="fp32").cpu().numpy()
+    check(Y, Yo, "fp32")
+    wide = np.zeros((A.shape[0], l + 1), np.float32)
+    wide[:, :l] = A
+    Ys = mds().embed_from_sqdist(model, dev(wide)[:, :l], prec="fp32").cpu().numpy()
+    check(Ys, Yo, "fp32")
+    assert errors.column_errors(Ys, Y)["maxabs_rms"] <= 1e-5
+    model.free()
+
+
 def test_batch_invariance_bitwise():
     X = gen.small_gaussian(3000, seed=7)
     D = l1_sqdist(X[:200], X[:200])
