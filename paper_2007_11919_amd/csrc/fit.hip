@@ -298,9 +298,23 @@ __global__ __launch_bounds__(1024) void k_finish(double* __restrict__ V, int64_t
 // w stays in LDS, wave g forms the dots of columns g, g + 16, ... (lanes
 // down the rows, fixed butterfly), and thread t updates rows t, t + 1024, ...
 // over the columns in order.  One launch per step instead of five.
+// The first pass's dots also copy the first ncache columns of V into LDS
+// (as many as fit beside w), so the update and the second pass read those
+// from LDS: each such column leaves memory once per step instead of four
+// times.  The copies are exact, so the sums are unchanged.
 constexpr int kOrthThreads = 1024;
 constexpr int kOrthMaxL = 4096;           // w and the dots in the default 64 KB of LDS
 constexpr int64_t kOrthMaxBasis = 40000;  // (j + 1) l values of V read per pass
+constexpr int kOrthLdsMax = 159 * 1024;   // dynamic LDS of one k_orth block (160 KB with red[])
+// columns of V that k_orth keeps in LDS for a step with nc columns
+__host__ __device__ inline int orth_cache_cols(int64_t l, int nc) {
+  const int64_t fixed = (int64_t)sizeof(double) * (l + 2 * (int64_t)nc);
+  const int64_t room = (kOrthLdsMax - fixed) / ((int64_t)sizeof(double) * l);
+  return (int)(room < 0 ? 0 : (room < nc ? room : nc));
+}
+inline size_t orth_lds_bytes(int64_t l, int nc) {
+  return sizeof(double) * (size_t)(l + 2 * (int64_t)nc + (int64_t)orth_cache_cols(l, nc) * l);
+}
 __global__ __launch_bounds__(kOrthThreads) void k_orth(double* __restrict__ V, int64_t l, int j,
                                                        const double* __restrict__ w_in,
                                                        double* __restrict__ h1, double* __restrict__ h2,
@@ -309,30 +323,49 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth(double* __restrict__ V, i
                                                        const double* __restrict__ qnorm,
                                                        int* __restrict__ ctrl, int write_next) {
   if (ctrl[0]) return;
-  extern __shared__ double ws[];  // l values of w, then the j + 1 dots of each pass
+  // LDS: l values of w, the j + 1 dots of each pass, then columns
+  // 0 .. ncache - 1 of V
+  extern __shared__ double ws[];
   __shared__ double red[kOrthThreads / 64];
-  double* hs = ws + l;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   constexpr int NW = kOrthThreads / 64;
   const int nc = j + 1;
+  const int ncache = orth_cache_cols(l, nc);
+  double* hs = ws + l;
+  double* vs = hs + 2 * nc;
   for (int64_t i = t; i < l; i += kOrthThreads) ws[i] = w_in[i];
   __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
     double* h = pass == 0 ? h1 : h2;
     double* hp = hs + pass * nc;
     for (int c = wv; c < nc; c += NW) {
-      const double* vc = V + (int64_t)c * l;
+      // the first pass reads the column from memory (and keeps a copy when
+      // it fits); the second reads the copy
+      const bool cached = c < ncache;
+      const double* vc = (pass == 1 && cached) ? vs + (int64_t)c * l : V + (int64_t)c * l;
+      double* keep = (pass == 0 && cached) ? vs + (int64_t)c * l : nullptr;
       // four independent sums (rows i, i + 64, i + 128, i + 192 mod 256),
       // combined in a fixed order
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       int64_t i = lane;
       for (; i + 192 < l; i += 256) {
-        s0 = fma(vc[i], ws[i], s0);
-        s1 = fma(vc[i + 64], ws[i + 64], s1);
-        s2 = fma(vc[i + 128], ws[i + 128], s2);
-        s3 = fma(vc[i + 192], ws[i + 192], s3);
+        const double a0 = vc[i], a1 = vc[i + 64], a2 = vc[i + 128], a3 = vc[i + 192];
+        if (keep) {
+          keep[i] = a0;
+          keep[i + 64] = a1;
+          keep[i + 128] = a2;
+          keep[i + 192] = a3;
+        }
+        s0 = fma(a0, ws[i], s0);
+        s1 = fma(a1, ws[i + 64], s1);
+        s2 = fma(a2, ws[i + 128], s2);
+        s3 = fma(a3, ws[i + 192], s3);
       }
-      for (; i < l; i += 64) s0 = fma(vc[i], ws[i], s0);
+      for (; i < l; i += 64) {
+        const double a0 = vc[i];
+        if (keep) keep[i] = a0;
+        s0 = fma(a0, ws[i], s0);
+      }
       double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -343,16 +376,24 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth(double* __restrict__ V, i
     }
     __syncthreads();
     for (int64_t i = t; i < l; i += kOrthThreads) {
-      // four independent sums over the columns (c mod 4), combined in order
+      // four independent sums over the columns (c mod 4), combined in order;
+      // whole groups of four held in LDS are read there, the rest from
+      // memory (the same values)
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       int c = 0;
+      for (; c + 3 < nc && c + 3 < ncache; c += 4) {
+        s0 = fma(vs[(int64_t)c * l + i], hp[c], s0);
+        s1 = fma(vs[(int64_t)(c + 1) * l + i], hp[c + 1], s1);
+        s2 = fma(vs[(int64_t)(c + 2) * l + i], hp[c + 2], s2);
+        s3 = fma(vs[(int64_t)(c + 3) * l + i], hp[c + 3], s3);
+      }
       for (; c + 3 < nc; c += 4) {
         s0 = fma(V[(int64_t)c * l + i], hp[c], s0);
         s1 = fma(V[(int64_t)(c + 1) * l + i], hp[c + 1], s1);
         s2 = fma(V[(int64_t)(c + 2) * l + i], hp[c + 2], s2);
         s3 = fma(V[(int64_t)(c + 3) * l + i], hp[c + 3], s3);
       }
-      for (; c < nc; ++c) s0 = fma(V[(int64_t)c * l + i], hp[c], s0);
+      for (; c < nc; ++c) s0 = fma(c < ncache ? vs[(int64_t)c * l + i] : V[(int64_t)c * l + i], hp[c], s0);
       ws[i] -= (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
@@ -954,6 +995,12 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   // ---- Lanczos with full reorthogonalisation ----
   const int upd_blocks = (int)((l + 63) / 64);
   const int fill_blocks = (int)((l + 255) / 256);
+  static bool orth_attr = false;  // k_orth may take all of a CU's LDS
+  if (!orth_attr) {
+    MDS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kOrthLdsMax));
+    orth_attr = true;
+  }
   k_fill_random<<<fill_blocks, 256, 0, st>>>(w, l, 0x5EEDull);
   k_set_column<<<1, 1024, 0, st>>>(Vk, l, 0, w, 0.0, ctrl + 2);
   LAUNCH_CHECK("lanczos start");
@@ -974,7 +1021,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
       const size_t shm = sizeof(double) * (size_t)(j + 1);
       k_symv<<<(unsigned)l, 256, 0, st>>>(DQ, l, Vk + (int64_t)j * l, w, ctrl);
       if (l <= kOrthMaxL && (int64_t)(j + 1) * l <= kOrthMaxBasis) {
-        k_orth<<<1, kOrthThreads, sizeof(double) * (size_t)(l + 2 * (j + 1)), st>>>(
+        k_orth<<<1, kOrthThreads, orth_lds_bytes(l, j + 1), st>>>(
             Vk, l, j, w, h1, h2, alpha, beta, scal + 1, ctrl, (j + 1 < kcap) ? 1 : 0);
         continue;
       }
