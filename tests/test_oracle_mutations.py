@@ -43,7 +43,7 @@ def test_unmutated_oracle_passes_all_checks():
 
 
 def _gower_with_V(fit, A2):
-    # reads the north-star "Q" as V instead of X1
+    # a plausible misreading of eq. (2): the eigenvectors V in place of X1
     l = fit.M.shape[0]
     s1_inv = np.where(fit.live, l / fit.lam, 0.0)
     return (1.0 / (2.0 * l)) * ((fit.q[None, :] - A2) @ fit.V) * s1_inv[None, :]
