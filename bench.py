@@ -673,8 +673,8 @@ def workload_run(mds, torch, name, args, dev, cpu):
     if cpu:
         log(f"[{name}] cpu baseline (oracle)")
         base, errs, fit_o, _, _ = cpu_baseline(
-            name, X, w, args.cpu_sample if name == "wide" else args.cpu_sample // 10,
-            100_000 if name == "wide" else 20_000,
+            name, X, w, args.cpu_sample,
+            100_000 if name == "wide" else 50_000,
             {"fp32": Y32.cpu().numpy(), "split_bf16": Ybf.cpu().numpy(),
              "split_fp16": Y16.cpu().numpy(), "fp64": Y64n})
         rep["cpu_baseline"] = base
