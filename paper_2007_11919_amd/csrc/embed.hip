@@ -133,7 +133,7 @@ __device__ void embed_tile(const EmbedModelView& mv, const TX* __restrict__ X, i
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 1;   // 64-row half
   const int wn = wave >> 1;  // 64-landmark half
   const int lr = lane & 15;
@@ -497,7 +497,7 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
   constexpr int E = 4;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 1;   // 64-row half
   const int wn = wave >> 1;  // 128-landmark quarter
   const int lr = lane & 15;
