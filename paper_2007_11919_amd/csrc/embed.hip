@@ -490,7 +490,11 @@ constexpr int kWaitVm0 = 0x0F70;
 // pairs share a 256-byte line) on distinct 16-byte slots
 __device__ inline int swz(int row, int seg) { return (seg ^ ((row >> 1) & 7)) << 4; }
 
-template <int MODE>
+// KTAIL: p may end inside a 16-value k-block, whose products past p are
+// skipped by uniform branches.  With p a multiple of 16 those branches
+// are always taken, so the form without them gives the same bits with
+// fewer branches in the product loop.
+template <int MODE, bool KTAIL>
 __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restrict__ X, int64_t ldx,
                                 int nrows, float* __restrict__ Y, int64_t ldy, char* lds) {
   static_assert(MODE == MODE_F32, "the split precisions run embed_tile_s3");
@@ -645,7 +649,7 @@ __device__ void embed_tile_wide(const EmbedModelView& mv, const float* __restric
         const f4 a = *reinterpret_cast<const f4*>(mb + lm * CHUNK_BYTES + swz(lm, 4 * kb + lg));
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
-          if (4 * jj < rem)
+          if (!KTAIL || 4 * jj < rem)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[jj], b[j][jj], acc[i][j]);
       }
@@ -1318,7 +1322,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(waves_p
   }
 }
 
-template <int MODE>
+template <int MODE, bool KTAIL>
 __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_wide(
     EmbedModelView mv, const float* __restrict__ X, int64_t n, int64_t ldx, float* __restrict__ Y,
     int64_t ldy) {
@@ -1327,7 +1331,7 @@ __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row0 = tile * BM;
     const int nrows = (int)((n - row0) < BM ? (n - row0) : BM);
-    embed_tile_wide<MODE>(mv, X + row0 * ldx, ldx, nrows, Y + row0 * ldy, ldy, lds);
+    embed_tile_wide<MODE, KTAIL>(mv, X + row0 * ldx, ldx, nrows, Y + row0 * ldy, ldy, lds);
   }
 }
 
@@ -1343,7 +1347,7 @@ __global__ __launch_bounds__(WTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2))
     const EmbedModelView mv = views[tw.model];
     const float* X = reinterpret_cast<const float*>(tw.x) + tw.row0 * tw.ldx;
     float* Y = reinterpret_cast<float*>(tw.y) + tw.row0 * tw.ldy;
-    embed_tile_wide<MODE>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);
+    embed_tile_wide<MODE, true>(mv, X, tw.ldx, tw.nrows, Y, tw.ldy, lds);  // models of any p
   }
 }
 
@@ -1400,9 +1404,11 @@ hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int
                          int64_t ldy, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed_wide<MODE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, WLDS_BYTES);
-    if (e != hipSuccess) return e;
+    for (const void* f : {reinterpret_cast<const void*>(&k_embed_wide<MODE, true>),
+                          reinterpret_cast<const void*>(&k_embed_wide<MODE, false>)}) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, WLDS_BYTES);
+      if (e != hipSuccess) return e;
+    }
     attr_set = true;
   }
   const int64_t ntiles = (n + BM - 1) / BM;
@@ -1410,8 +1416,12 @@ hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int
   // gridDim apart; lane constants are computed (and spilled) once per block
   const int64_t cap = (int64_t)num_cu();
   const int grid = (int)(ntiles < cap ? ntiles : cap);
-  k_embed_wide<MODE><<<grid, WTHREADS, WLDS_BYTES, st>>>(mv, reinterpret_cast<const float*>(X), n,
-                                                             ldx, reinterpret_cast<float*>(Y), ldy);
+  if (mv.p % 16 != 0)
+    k_embed_wide<MODE, true><<<grid, WTHREADS, WLDS_BYTES, st>>>(
+        mv, reinterpret_cast<const float*>(X), n, ldx, reinterpret_cast<float*>(Y), ldy);
+  else
+    k_embed_wide<MODE, false><<<grid, WTHREADS, WLDS_BYTES, st>>>(
+        mv, reinterpret_cast<const float*>(X), n, ldx, reinterpret_cast<float*>(Y), ldy);
   return hipGetLastError();
 }
 

@@ -111,3 +111,26 @@ def test_wide_fp32_serving_matches_plain():
         Yo, scale = refs[which]
         check_rows(Y.cpu().numpy(), Yo[off:off + Xs.shape[0]], scale, prec)
     srv.close()
+
+
+def test_whole_kblocks_serving_matches_plain():
+    """p a multiple of 16: the plain launch takes the form without the
+    ragged-k-block branches and the serving launch the general form; the
+    branches are always taken there, so the two give the same bits."""
+    from paper_2007_11919_amd import serve
+    m = mds()
+    X = torch.from_numpy(gaussian(4000, 64, seed=33)).cuda()
+    model = m.fit_landmarks(X, 1000, 10, seed=4)  # 512-landmark variant in FP32
+    srv = serve.Server(budget_bytes=2 << 30, max_slots=4, tiles_per_step=64)
+    mid = srv.add_model(model)
+    jobs = []
+    for off, n in [(0, 4000), (5, 700), (1234, 129)]:
+        Y = torch.full((n, model.r), float("nan"), device="cuda")
+        jobs.append((off, n, Y, srv.submit(mid, X[off:off + n], "fp32", Y)))
+    for *_, t in jobs:
+        srv.wait(t, timeout=120.0)
+    for off, n, Y, _ in jobs:
+        ref = m.embed(model, X[off:off + n], prec="fp32")
+        torch.cuda.synchronize()
+        assert torch.equal(Y, ref), (off, n)
+    srv.close()
