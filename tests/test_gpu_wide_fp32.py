@@ -47,7 +47,8 @@ def gaussian(n, p, seed, extra=0):
     (47, 0, 1024, 5, False),     # p % 4 = 3: tail k-block of 15 values, scalar loads
     (784, 0, 2000, 10, False),   # the image shape with Gaussian values
     (64, 4, 1024, 10, False),    # 16-byte aligned strided rows: data chunks copied straight to LDS
-], ids=["p100", "p101-strided", "p3", "p16-l1300", "p47", "p784", "p64-strided"])
+    (48, 3, 1024, 10, False),    # whole k-blocks (no ragged-block branches) from unaligned rows
+], ids=["p100", "p101-strided", "p3", "p16-l1300", "p47", "p784", "p64-strided", "p48-oddstride"])
 def test_wide_fp32_matches_oracle(p, extra, l, r, weak):
     n = 2500
     Xw = gaussian(n, p, seed=p, extra=extra)
