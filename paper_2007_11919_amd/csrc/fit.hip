@@ -221,6 +221,38 @@ __global__ __launch_bounds__(256) void k_symv(const double* __restrict__ Q, int6
   if (threadIdx.x == 0) w[row] = s;
 }
 
+// w = Q v for l <= kSymvRowsMaxL: v staged in LDS once per block, one row
+// per wave (four rows per block), four independent sums per lane combined
+// in a fixed order, then a fixed butterfly over the wave.  Against one
+// block per row, each block reads v from L2 once for four rows.  For
+// larger l one block per row (k_symv) keeps more of Q in flight.
+constexpr int64_t kSymvRowsMaxL = 1024;
+__global__ __launch_bounds__(256) void k_symv_rows(const double* __restrict__ Q, int64_t l,
+                                                   const double* __restrict__ v,
+                                                   double* __restrict__ w, const int* __restrict__ ctrl) {
+  if (ctrl[0]) return;
+  extern __shared__ double vs[];
+  for (int64_t i = threadIdx.x; i < l; i += 256) vs[i] = v[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= l) return;
+  const double* qr = Q + row * l;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t c = lane;
+  for (; c + 192 < l; c += 256) {
+    s0 = fma(qr[c], vs[c], s0);
+    s1 = fma(qr[c + 64], vs[c + 64], s1);
+    s2 = fma(qr[c + 128], vs[c + 128], s2);
+    s3 = fma(qr[c + 192], vs[c + 192], s3);
+  }
+  for (; c < l; c += 64) s0 = fma(qr[c], vs[c], s0);
+  double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) w[row] = s;
+}
+
 // h_c = V_c' w for c < ncols (one block per column)
 __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int64_t l,
                                               const double* __restrict__ w, double* __restrict__ h,
@@ -1019,7 +1051,11 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
     const int jend = std::min(kcap, j + batch);
     for (; j < jend; ++j) {
       const size_t shm = sizeof(double) * (size_t)(j + 1);
-      k_symv<<<(unsigned)l, 256, 0, st>>>(DQ, l, Vk + (int64_t)j * l, w, ctrl);
+      if (l <= kSymvRowsMaxL)
+        k_symv_rows<<<(unsigned)((l + 3) / 4), 256, sizeof(double) * (size_t)l, st>>>(DQ, l, Vk + (int64_t)j * l,
+                                                                                    w, ctrl);
+      else
+        k_symv<<<(unsigned)l, 256, 0, st>>>(DQ, l, Vk + (int64_t)j * l, w, ctrl);
       if (l <= kOrthMaxL && (int64_t)(j + 1) * l <= kOrthMaxBasis) {
         k_orth<<<1, kOrthThreads, orth_lds_bytes(l, j + 1), st>>>(
             Vk, l, j, w, h1, h2, alpha, beta, scal + 1, ctrl, (j + 1 < kcap) ? 1 : 0);
