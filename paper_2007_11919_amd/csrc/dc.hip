@@ -1103,7 +1103,7 @@ size_t eigen_reg_lds_bytes(int d, int nr) {
 hipError_t set_eigen_reg_attrs() {
   hipError_t e = hipSuccess;
   auto set = [&](const void* f) {
-    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax);
+    if (e == hipSuccess) e = lds_limit_once(f, (int)kDcLdsMax);
   };
   set(reinterpret_cast<const void*>(&k_dc_eigen_reg<1>));
   set(reinterpret_cast<const void*>(&k_dc_eigen_reg<2>));
@@ -1183,17 +1183,10 @@ mds_status dc_run(const TX* X, int64_t ldx, DcShape s, uint64_t seed, double* Y,
     k_dc_mean<TX><<<grid, 256, 0, st>>>(X, ldx, order, s, mean.get<double>(), bad.get<int>());
     DC_LAUNCH("part means");
   }
-  static bool attr_set = false;
-  if (!attr_set) {
-    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
-    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
-    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_align),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
-    DC_HIP(set_eigen_reg_attrs());
-    attr_set = true;
-  }
+  DC_HIP(lds_limit_once(reinterpret_cast<const void*>(&k_dc_eigen<true>), (int)kDcLdsMax));
+  DC_HIP(lds_limit_once(reinterpret_cast<const void*>(&k_dc_eigen<false>), (int)kDcLdsMax));
+  DC_HIP(lds_limit_once(reinterpret_cast<const void*>(&k_dc_align), (int)kDcLdsMax));
+  DC_HIP(set_eigen_reg_attrs());
   for (int64_t j0 = 0; j0 < np; j0 += chunk) {
     const int64_t cnt = std::min(chunk, np - j0);
     const unsigned tiles = (unsigned)((d + 63) / 64);
@@ -1274,15 +1267,9 @@ mds_status dense_top_eigen(double* G, int d, int r, double* lam, double* U, int*
   s.nparts = 1;
   s.m_max = d;
   const int nr = std::min(r, d);
-  static bool attr_set = false;
-  if (!attr_set) {
-    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
-    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dc_eigen<false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDcLdsMax));
-    DC_HIP(set_eigen_reg_attrs());
-    attr_set = true;
-  }
+  DC_HIP(lds_limit_once(reinterpret_cast<const void*>(&k_dc_eigen<true>), (int)kDcLdsMax));
+  DC_HIP(lds_limit_once(reinterpret_cast<const void*>(&k_dc_eigen<false>), (int)kDcLdsMax));
+  DC_HIP(set_eigen_reg_attrs());
   if (d <= kDcRegMaxD && eigen_reg_lds_bytes(d, nr) <= kDcLdsMax) {
     launch_eigen_reg(1, eigen_reg_lds_bytes(d, nr), st, G, d, s, 0, 0, nr, lam, U, nullptr, status);
   } else if (eigen_lds_bytes(d, nr) <= kDcLdsMax) {

@@ -1384,12 +1384,9 @@ __global__ __launch_bounds__(S3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 template <int MODE, typename TX, int RB>
 hipError_t launch_t(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                     int64_t ldy, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed<MODE, TX, RB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+  {
+    hipError_t e = lds_limit_once(reinterpret_cast<const void*>(&k_embed<MODE, TX, RB>), LDS_BYTES);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   const int64_t ntiles = (n + BM - 1) / BM;
   const int64_t cap = (int64_t)num_cu() * 2 * 64;
@@ -1402,14 +1399,10 @@ hipError_t launch_t(const EmbedModelView& mv, const void* X, int64_t n, int64_t 
 template <int MODE>
 hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                          int64_t ldy, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    for (const void* f : {reinterpret_cast<const void*>(&k_embed_wide<MODE, true>),
-                          reinterpret_cast<const void*>(&k_embed_wide<MODE, false>)}) {
-      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, WLDS_BYTES);
-      if (e != hipSuccess) return e;
-    }
-    attr_set = true;
+  for (const void* f : {reinterpret_cast<const void*>(&k_embed_wide<MODE, true>),
+                        reinterpret_cast<const void*>(&k_embed_wide<MODE, false>)}) {
+    hipError_t e = lds_limit_once(f, WLDS_BYTES);
+    if (e != hipSuccess) return e;
   }
   const int64_t ntiles = (n + BM - 1) / BM;
   // persistent: one block per CU (the LDS holds one), each walking tiles
@@ -1428,12 +1421,9 @@ hipError_t launch_wide_v(const EmbedModelView& mv, const void* X, int64_t n, int
 template <int MODE, bool HI, bool XDMA>
 hipError_t launch_s3(const EmbedModelView& mv, const void* X, int64_t n, int64_t ldx, void* Y,
                      int64_t ldy, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_embed_s3<MODE, HI, XDMA>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, s3_lds<HI>());
+  {
+    hipError_t e = lds_limit_once(reinterpret_cast<const void*>(&k_embed_s3<MODE, HI, XDMA>), s3_lds<HI>());
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   const int64_t ntiles = (n + BM - 1) / BM;
   const int64_t cap = (int64_t)num_cu();
@@ -1582,7 +1572,6 @@ const void* worklist_fn(int mode, int rbc) {
     default: return nullptr;
   }
 }
-bool g_work_attr[4][kEmbedClasses] = {};
 
 template <int MODE>
 void launch_work_rb(int rbc, int grid, hipStream_t st, const EmbedModelView* v, const TileWork* w,
@@ -1622,14 +1611,11 @@ int embed_blocks_per_cu(int mode, int rbc) {
 mds_status prepare_embed_worklist(int mode, int rbc) {
   const void* fn = worklist_fn(mode, rbc);
   if (!fn) return set_error(MDS_ERR_INVALID_ARG, "serving supports FP32 and split precisions");
-  if (!g_work_attr[mode][rbc]) {
-    const int bytes = rbc < kWideClass ? LDS_BYTES
-                      : mode == MODE_F32 ? WLDS_BYTES
-                      : rbc == kWideHiClass ? s3_lds<true>() : s3_lds<false>();
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-    g_work_attr[mode][rbc] = true;
-  }
+  const int bytes = rbc < kWideClass ? LDS_BYTES
+                    : mode == MODE_F32 ? WLDS_BYTES
+                    : rbc == kWideHiClass ? s3_lds<true>() : s3_lds<false>();
+  hipError_t e = lds_limit_once(fn, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   return MDS_OK;
 }
 

@@ -851,12 +851,9 @@ hipError_t launch_tridiag(const double* alpha, const double* beta, const int* ct
                           int* kout, hipStream_t st, double* report = nullptr,
                           const double* qn = nullptr, int d_probe = 0, double* theta2 = nullptr,
                           double* bound2 = nullptr, double* S2 = nullptr, double* gwork2 = nullptr) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tridiag),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTriLdsMax);
+  {
+    hipError_t e = lds_limit_once(reinterpret_cast<const void*>(&k_tridiag), (int)kTriLdsMax);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const int nr = std::min(r, k_host);
   const size_t base = sizeof(double) * 3 * (size_t)k_host;
@@ -1027,12 +1024,7 @@ mds_status fit_on_device(Model& m, const void* X, int dt, int64_t ldx, const int
   // ---- Lanczos with full reorthogonalisation ----
   const int upd_blocks = (int)((l + 63) / 64);
   const int fill_blocks = (int)((l + 255) / 256);
-  static bool orth_attr = false;  // k_orth may take all of a CU's LDS
-  if (!orth_attr) {
-    MDS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kOrthLdsMax));
-    orth_attr = true;
-  }
+  MDS_HIP(lds_limit_once(reinterpret_cast<const void*>(&k_orth), kOrthLdsMax));  // up to all of a CU's LDS
   k_fill_random<<<fill_blocks, 256, 0, st>>>(w, l, 0x5EEDull);
   k_set_column<<<1, 1024, 0, st>>>(Vk, l, 0, w, 0.0, ctrl + 2);
   LAUNCH_CHECK("lanczos start");

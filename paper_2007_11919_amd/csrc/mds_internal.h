@@ -5,7 +5,10 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <set>
 #include <string>
+#include <utility>
 
 #include "../../include/mds.h"
 
@@ -175,6 +178,22 @@ mds_status launch_embed_worklist(int mode, int rbc, const EmbedModelView* views_
                                  const TileWork* work_dev, const int32_t* nwork_dev,
                                  int grid, hipStream_t st);
 int embed_max_rb();
+// Raises kernel fn's dynamic LDS limit to bytes on the current device,
+// once per (kernel, device): the limit is a per-device setting, so a
+// process that uses several devices sets it on each.  Host only; safe from
+// several threads.
+inline hipError_t lds_limit_once(const void* fn, int bytes) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({fn, dev})) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done.insert({fn, dev});
+  return e;
+}
 // compute units of the current device (cached)
 int num_cu();
 int rb_class(int rb);

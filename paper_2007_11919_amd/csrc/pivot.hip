@@ -884,13 +884,8 @@ mds_status pivot_run(const TX* X, int dt, int64_t ldx, int64_t n, int64_t p, int
     PV_HIP(alloc(G, sizeof(double) * p * p));
     PV_HIP(alloc(U, sizeof(double) * p * r));
     PV_HIP(alloc(cflag, sizeof(int)));
-    static bool chol_attr = false;
-    if (!chol_attr) {
-      PV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)(sizeof(double) * PV_CHOL_MAXP * (PV_CHOL_MAXP + 1))));
-      chol_attr = true;
-    }
+    PV_HIP(lds_limit_once(reinterpret_cast<const void*>(&k_chol),
+                          (int)(sizeof(double) * PV_CHOL_MAXP * (PV_CHOL_MAXP + 1))));
     k_chol<<<1, 1024, sizeof(double) * (size_t)p * (p + 1), st>>>(S.get<double>(), (int)p, Lc.get<double>(),
                                                                    cflag.get<int>());
     k_mc_l<<<(unsigned)((l * p + 255) / 256), 256, 0, st>>>(Mc.get<double>(), Lc.get<double>(), l, p,
